@@ -1,0 +1,217 @@
+"""Benchmark: hybrid BFS GTEPS on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat24]
+
+A step is one pass of the single-source search from each of the workload's
+sources (64 for RMAT scale 24).  GTEPS per source = m_s / t_s with m_s the
+undirected edges of the source's component and t_s the median wall time of
+its bfs_run call over the timed steps; `value` is their harmonic mean.  The
+graph is resident in HBM before timing starts.  Prints one JSON line.
+
+The dominant kernel is the bottom-up level kernel: its average duration is
+taken from HIP events recorded around every bottom-up launch in the timed
+steps, and its algorithmic bytes per launch from the byte model (visited,
+row-offset, neighbour-id, frontier and output bytes the level must move).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS (harmonic mean, 64 sources) RMAT-24; batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator call, number of sources, row offsets int32?)
+    "rmat24": ("rmat", 24, 64, False),
+    "rmat22": ("rmat", 22, 64, False),
+    "rmat16": ("rmat", 16, 16, True),
+    "grid4096": ("grid", 4096, 16, False),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_graph(name):
+    import graphgen
+    kind, size, nsrc, rp32 = WORKLOADS[name]
+    g = graphgen.rmat(size) if kind == "rmat" else graphgen.grid(size)
+    return g, graphgen.sources(g, nsrc), rp32
+
+
+def bu_launch_bytes(lv, n, row_ptr_bytes, with_parent=True):
+    """Algorithmic bytes of one bottom-up level: visited words read, row
+    bounds of the scanned vertices, neighbour ids up to the first hit,
+    frontier bits, next-frontier and visited words written, dist (and parent)
+    of the vertices found."""
+    B = 8 * ((n + 63) // 64)
+    p = 4 if with_parent else 0
+    return (B + row_ptr_bytes * min(n + 1, 2 * lv["scanned"]) + 4 * lv["examined"] + B + 2 * B
+            + (4 + p) * lv["discovered"])
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    h.update(open(os.path.join(ROOT, "paper_2503_00430_amd", "csrc", "single.hip"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per bottom-up launch from the committed rocprofv3 counter
+    summary, or None when it is absent or the kernel source has changed."""
+    path = os.path.join(ROOT, "profiles", f"k_bu_{workload}_traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(g, sources, budget_s=20.0, max_sources=8):
+    """The oracle (serial C BFS, one thread) on a bounded sample of sources."""
+    import oracle
+    teps, used = [], []
+    t_total = 0.0
+    for s in sources[:max_sources]:
+        d, _, secs = oracle.bfs_timed(g, int(s), want_parent=True)
+        st = oracle.level_stats(g, d)
+        teps.append(st["m_s"] / secs)
+        used.append(int(s))
+        t_total += secs
+        if t_total > budget_s:
+            break
+    hm = len(teps) / sum(1.0 / t for t in teps)
+    return {"value": hm / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(used)} of the {len(sources)} sources on the full graph, "
+                      f"serial FIFO BFS with parents, {t_total:.1f} s of CPU time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the search runs on a single device).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2503_00430_amd as bfs
+    if not os.path.exists(bfs.library_path()):
+        from paper_2503_00430_amd import build as libbuild
+        libbuild.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    t0 = time.time()
+    g, sources, rp32 = make_graph(args.workload)
+    log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f} s")
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, bfs.BFS_ROWPTR32 if rp32 else 0)
+    info = bfs.bfs_graph_info_get(gh)
+    bfs.bfs_set_params(gh, collect_timing=1)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def step(record):
+        for s in sources:
+            bfs.bfs_run(gh, int(s), dist, parent)
+            if record is not None:
+                run, levels = bfs.bfs_get_run_stats(gh)
+                record.append((int(s), run, levels))
+
+    for _ in range(args.warmup):
+        step(None)
+    log("warmup done")
+    records = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(records)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    log(f"timed {args.steps} steps in {t_end - t_start:.3f} s")
+
+    # per-source median wall time -> TEPS; harmonic mean over sources
+    per_src = {}
+    for s, run, _ in records:
+        per_src.setdefault(s, {"edges": run["edges"], "t": []})["t"].append(run["host_ms"] / 1e3)
+    teps = [v["edges"] / statistics.median(v["t"]) for v in per_src.values()]
+    gteps_hm = len(teps) / sum(1.0 / t for t in teps) / 1e9
+    dev_teps = []
+    for s in per_src:
+        dts = [run["device_ms"] / 1e3 for s2, run, _ in records if s2 == s]
+        dev_teps.append(per_src[s]["edges"] / statistics.median(dts))
+    gteps_dev_hm = len(dev_teps) / sum(1.0 / t for t in dev_teps) / 1e9
+
+    # level breakdown and the bottom-up kernel's roofline
+    runs = len(records)
+    td_ms = sum(lv["ms"] for _, _, lvs in records for lv in lvs if lv["direction"] == 0) / runs
+    bu_levels = [lv for _, _, lvs in records for lv in lvs if lv["direction"] == 1]
+    bu_ms = sum(lv["ms"] for lv in bu_levels) / runs
+    roofline = None
+    if bu_levels:
+        avg_s = statistics.mean(lv["ms"] for lv in bu_levels) / 1e3
+        avg_bytes = statistics.mean(bu_launch_bytes(lv, g.n, info["row_ptr_bytes"]) for lv in bu_levels)
+        achieved = avg_bytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(args.workload), "kernel": "k_bu",
+                    "avg_launch_us": round(avg_s * 1e6, 2),
+                    "algo_bytes_per_launch": int(avg_bytes), "launches": len(bu_levels)}
+    schedules = {}
+    for _, _, lvs in records[: len(sources)]:
+        key = "".join("TB"[lv["direction"]] for lv in lvs)
+        schedules[key] = schedules.get(key, 0) + 1
+
+    out = {
+        "metric": METRIC,
+        "value": round(gteps_hm, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t_end - t_start) * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}_plain_hybrid_bfs", "n": g.n, "nnz": g.nnz,
+                   "sources": len(sources), "row_ptr_bytes": info["row_ptr_bytes"],
+                   "policy": "auto (alpha/beta 14/24 for average degree >= 7, else top-down only)",
+                   "parents": True},
+        "roofline": roofline,
+        "gteps_device_time_hm": round(gteps_dev_hm, 3),
+        "td_ms_per_bfs": round(td_ms, 4),
+        "bu_ms_per_bfs": round(bu_ms, 4),
+        "direction_schedules": schedules,
+    }
+    gh.close()
+    del dist, parent
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, sources)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

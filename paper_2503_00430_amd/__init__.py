@@ -1,0 +1,18 @@
+"""Python binding of libbfs (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/bfs.h).  PyTorch supplies device memory (output tensors) and
+streams; all graph work runs in the library's HIP kernels.  The library
+must be built (`python -m paper_2503_00430_amd.build`); importing fails
+loudly when it is missing.
+"""
+from ._lib import (  # noqa: F401
+    BFS_INPUT_DEVICE, BFS_VALIDATE, BFS_VALIDATE_SYMMETRY, BFS_ROWPTR32,
+    BFS_POLICY_AUTO, BFS_POLICY_ALPHA_BETA, BFS_POLICY_FRONTIER_5PCT, BFS_POLICY_TD_ONLY,
+    BFS_LOOP_AUTO, BFS_LOOP_HOST, BFS_LOOP_GRAPH,
+    BFS_REQ_QUEUED, BFS_REQ_RUNNING, BFS_REQ_DONE, BFS_REQ_FAILED,
+    BfsError, Graph, Server, library_path, load_library,
+    bfs_create_graph, bfs_destroy_graph, bfs_graph_set_stream, bfs_set_params, bfs_get_params,
+    bfs_default_params, bfs_graph_info_get, bfs_run, bfs_get_run_stats, bfs_run_batch,
+    bfs_serve_create, bfs_serve_destroy, bfs_serve_submit, bfs_serve_poll, bfs_last_error,
+)

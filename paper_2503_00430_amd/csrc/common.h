@@ -1,0 +1,165 @@
+// Internal declarations of libbfs (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+
+namespace bfsmi {
+
+constexpr int kWave = 64;
+
+enum Dir : int32_t { kTD = 0, kBU = 1 };
+enum Conv : int32_t { kConvNone = 0, kConvQ2B = 1, kConvB2Q = 2 };
+enum Bucket : int32_t { kSmall = 0, kMedium = 1, kLarge = 2 };
+
+// Per-level record written on the device by the decide step.
+struct LevelRec {
+  int32_t level, dir;
+  int64_t n_f, m_f, m_u, found, scanned, examined;
+};
+
+// Device-resident control block of one single-source search.  The level
+// state is written only by the single-thread decide step (and by the init
+// kernel); the accumulators are added to by the level kernels and cleared by
+// decide.  Every kernel reads what it needs from here, so a captured
+// sequence of kernels stays valid from level to level.
+struct alignas(256) Ctl {
+  int32_t level;   // level about to run: expands vertices at distance `level`
+  int32_t dir;     // its direction (kTD / kBU)
+  int32_t done;    // nonzero once a level found nothing
+  int32_t qcur;    // queue set holding the current frontier
+  int32_t bcur;    // bitmap holding the current frontier
+  int32_t conv;    // frontier conversion to perform before `level` runs
+  int32_t policy;  // resolved bfs_policy (never AUTO)
+  int32_t alpha, beta;
+  int32_t rec_cap;  // capacity of the LevelRec array
+  int32_t levels_done;
+  int32_t pad0;
+  int64_t n;        // vertex count
+  int64_t n_f;      // size of the current frontier
+  int64_t m_f;      // sum of degrees over the current frontier
+  int64_t m_u;      // sum of degrees over vertices not yet visited
+  int64_t sum_mf;   // sum of m_f over all levels so far (= 2 * TEPS edge count)
+  int64_t reached;  // vertices visited so far
+  unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
+  unsigned int pad1[2];
+  unsigned long long acc_found;     // vertices discovered by the running level
+  unsigned long long acc_found_deg; // sum of their degrees
+  unsigned long long acc_scanned;   // bottom-up: unvisited vertices examined
+  unsigned long long acc_examined;  // bottom-up: neighbours examined
+  int32_t *dist;    // outputs of the current search
+  int32_t *parent;
+};
+
+// Everything a single-source kernel needs, passed by value.
+template <class RowT>
+struct DevG {
+  const RowT *rp;
+  const int32_t *col;
+  const uint64_t *iso;  // bit set: vertex has degree 0, or id >= n (tail of last word)
+  uint64_t *vis;        // visited bitmap
+  uint64_t *bm[2];      // frontier bitmaps (current / next alternate)
+  int32_t *qs[2];       // queue sets: small-degree vertices
+  int32_t *qm[2];       //             medium-degree vertices
+  uint64_t *ql[2];      //             large-degree vertices, one entry per chunk: chunk << 32 | v
+  Ctl *ctl;
+  LevelRec *recs;
+  int64_t n;
+  int64_t words;        // 64-bit words per bitmap
+  int32_t t1, t2, tbu;  // degree thresholds (td_wave_degree, td_block_degree, bu_wave_degree)
+};
+
+// Scratch of the batched (multi-source) search, allocated on first use.
+struct MsScratch {
+  uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+  unsigned long long *counters = nullptr;
+  int64_t words = 0;
+  size_t bytes = 0;
+};
+
+}  // namespace bfsmi
+
+struct bfs_graph {
+  int device = 0;
+  int64_t n = 0, nnz = 0, words = 0;
+  bool rp64 = true;
+  void *rp = nullptr;
+  int32_t *col = nullptr;
+  uint64_t *iso = nullptr;
+  uint64_t *vis = nullptr;
+  uint64_t *bm[2] = {nullptr, nullptr};
+  int32_t *qs[2] = {nullptr, nullptr};
+  int32_t *qm[2] = {nullptr, nullptr};
+  uint64_t *ql[2] = {nullptr, nullptr};
+  int64_t ql_cap = 0;
+  bfsmi::Ctl *ctl = nullptr;
+  bfsmi::Ctl *ctl_host = nullptr;  // pinned mirror
+  bfsmi::LevelRec *recs = nullptr;
+  int32_t rec_cap = 0;
+  int64_t isolated = 0, max_degree = 0;
+  int64_t device_bytes = 0;
+  hipStream_t stream = nullptr;      // caller's stream (null stream by default)
+  hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  std::vector<hipEvent_t> level_events;
+  bfs_params params{};
+  std::mutex mu;
+  std::atomic<int> server_refs{0};
+  // last run
+  bfs_run_stats last{};
+  std::vector<bfs_level_stats> last_levels;
+  // captured level loop
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int gexec_levels = 0;
+  // batched search
+  bfsmi::MsScratch ms;
+};
+
+namespace bfsmi {
+
+// Error reporting (thread-local message; returns `code`).
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+// Sets the graph's device current for the lifetime of the guard.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+int resolved_policy(const bfs_graph *g);
+int alloc_single_scratch(bfs_graph *g);  // (re)allocates the large-vertex queues
+void release_graph_exec(bfs_graph *g);
+
+// Single-source search (single.hip).
+int run_single(bfs_graph *g, int32_t source, int32_t *dist, int32_t *parent);
+
+// Batched search (msbfs.hip).  `stream` overrides the graph's stream when
+// not null.  Writes k rows of uint8 distances.
+int run_batch(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t stream);
+
+}  // namespace bfsmi
+
+#define BFS_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::bfsmi::fail(BFS_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)

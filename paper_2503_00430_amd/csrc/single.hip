@@ -1,0 +1,740 @@
+// Single-source direction-optimizing BFS on gfx950.
+//
+// The search is level-synchronous (Section 2, Listing 1): level L expands
+// the vertices at distance L and discovers those at distance L + 1.  Each
+// level runs in one of two directions (Section 2, BFS-Hybrid):
+//   top-down  - every frontier vertex examines its neighbours; a neighbour
+//               whose visited bit is clear is claimed with one atomicOr on
+//               its 64-bit visited word, and the winner stores dist and
+//               parent with plain stores (Section 2, BFS-NonAtomic: no
+//               atomic on the distance) and appends the vertex to the next
+//               frontier queue;
+//   bottom-up - every unvisited vertex scans its own row for a neighbour in
+//               the frontier bitmap and stops at the first hit (Section 2,
+//               Listing 2).
+// Visited state lives in a bitmap (Section 2, BFS-VisitedBitmap).  A bit of
+// a packed bitmap is never set with a plain read-modify-write from two
+// threads: top-down uses atomicOr, bottom-up gives each 64-vertex word to
+// one wavefront, which alone writes it.
+//
+// Mapping onto CDNA4 (wave64):
+//   * top-down work is split by degree: one thread per vertex of degree
+//     <= t1, one wavefront per vertex of degree in (t1, t2], and one
+//     workgroup per t2-edge chunk of larger vertices, so neighbour ids are
+//     read from HBM in coalesced runs and hubs do not serialise a wave;
+//   * discoveries are appended with one atomicAdd per wavefront and bucket
+//     (ballot + mbcnt give each lane its slot);
+//   * bottom-up gives a wavefront one 64-bit visited word (64 consecutive
+//     vertices): rows of degree <= tbu are scanned by their own lane, longer
+//     rows by the whole wavefront 64 neighbours at a time with a ballot
+//     early exit; the found mask is written by lane 0 as the next-frontier
+//     word and OR-ed into the visited word;
+//   * frontier counts and degree sums are reduced per workgroup and added to
+//     the device control block, where a single-thread kernel applies the
+//     direction rule (Section 2: alpha/beta of BFS-Hybrid dagger, or the 5 %
+//     frontier rule of BFS-Hybrid; Section 3: top-down only below average
+//     degree 7) and converts the frontier between queue and bitmap form when
+//     the direction changes.
+// Every kernel reads the level state from the control block, so the same
+// kernels serve a host-driven loop and a captured hipGraph of many levels.
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "common.h"
+
+namespace bfsmi {
+namespace {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of `m` below the calling lane.
+__device__ __forceinline__ unsigned lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Adds the workgroup totals of K per-thread counters to K device counters
+// (one atomic per workgroup and counter).  Every thread of the workgroup
+// must call it.
+template <int K>
+__device__ void block_accumulate(const unsigned long long (&v)[K], unsigned long long *const (&dst)[K]) {
+  __shared__ unsigned long long part[K][16];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    unsigned long long s = wave_sum(v[k]);
+    if (lane_id() == 0) part[k][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    unsigned long long t = 0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) t += part[threadIdx.x][i];
+    if (t) atomicAdd(dst[threadIdx.x], t);
+  }
+}
+
+// Claims vertex v: true for exactly one caller per search.
+__device__ __forceinline__ bool claim(uint64_t *vis, int32_t v) {
+  const uint64_t bit = 1ull << (v & 63);
+  unsigned long long *w = reinterpret_cast<unsigned long long *>(vis + (v >> 6));
+  if (*w & bit) return false;  // already visited (a stale read only costs the atomic below)
+  return !(atomicOr(w, (unsigned long long)bit) & bit);
+}
+
+template <class RowT>
+__device__ __forceinline__ int bucket_of(const DevG<RowT> &G, int64_t deg) {
+  return deg <= G.t1 ? kSmall : (deg <= G.t2 ? kMedium : kLarge);
+}
+
+// Appends the lanes' discovered vertices to queue set `qn`, split by degree
+// class.  Must be called by all lanes of a wavefront together.
+template <class RowT>
+__device__ __forceinline__ void wave_append(const DevG<RowT> &G, int qn, bool found, int32_t v, int64_t deg) {
+  const int b = found ? bucket_of(G, deg) : -1;
+  Ctl *c = G.ctl;
+#pragma unroll
+  for (int bb = kSmall; bb <= kMedium; ++bb) {
+    const uint64_t m = __ballot(b == bb);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned base = 0;
+      if (lane_id() == leader) base = atomicAdd(&c->qcnt[qn][bb], (unsigned)__popcll(m));
+      base = __shfl(base, leader);
+      if (b == bb) {
+        int32_t *q = (bb == kSmall) ? (qn ? G.qs[1] : G.qs[0]) : (qn ? G.qm[1] : G.qm[0]);
+        q[base + lanes_below(m)] = v;
+      }
+    }
+  }
+  if (b == kLarge) {  // rare: one entry per t2-edge chunk
+    const unsigned nch = (unsigned)((deg + G.t2 - 1) / G.t2);
+    const unsigned base = atomicAdd(&c->qcnt[qn][kLarge], nch);
+    uint64_t *q = qn ? G.ql[1] : G.ql[0];
+    for (unsigned k = 0; k < nch; ++k) q[base + k] = ((uint64_t)k << 32) | (uint32_t)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: dist = -1, parent = -1, visited = isolated-vertex mask,
+// then the source at level 0 in queue set 0 (the first level is top-down).
+
+template <class RowT>
+__global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
+                       int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = tid; i < G.n; i += stride) {
+    dist[i] = (i == s) ? 0 : -1;
+    if (parent) parent[i] = (i == s) ? s : -1;
+  }
+  const int64_t sw = s >> 6;
+  const uint64_t sb = 1ull << (s & 63);
+  for (int64_t w = tid; w < G.words; w += stride) G.vis[w] = G.iso[w] | (w == sw ? sb : 0ull);
+  if (tid == 0) {
+    Ctl *c = G.ctl;
+    const int64_t deg = (int64_t)G.rp[s + 1] - (int64_t)G.rp[s];
+    c->level = 0;
+    c->dir = kTD;
+    c->done = 0;
+    c->qcur = 0;
+    c->bcur = 0;
+    c->conv = kConvNone;
+    c->policy = policy;
+    c->alpha = alpha;
+    c->beta = beta;
+    c->rec_cap = rec_cap;
+    c->levels_done = 0;
+    c->n = G.n;
+    c->n_f = 1;
+    c->m_f = deg;
+    c->m_u = nnz - deg;
+    c->sum_mf = 0;
+    c->reached = 1;
+    for (int q = 0; q < 2; ++q)
+      for (int b = 0; b < 3; ++b) c->qcnt[q][b] = 0;
+    const int b = bucket_of(G, deg);
+    if (b == kLarge) {
+      const unsigned nch = (unsigned)((deg + G.t2 - 1) / G.t2);
+      for (unsigned k = 0; k < nch; ++k) G.ql[0][k] = ((uint64_t)k << 32) | (uint32_t)s;
+      c->qcnt[0][kLarge] = nch;
+    } else {
+      (b == kSmall ? G.qs[0] : G.qm[0])[0] = s;
+      c->qcnt[0][b] = 1;
+    }
+    c->acc_found = c->acc_found_deg = c->acc_scanned = c->acc_examined = 0;
+    c->dist = dist;
+    c->parent = parent;
+  }
+}
+
+// Discovery step shared by the top-down kernels: lane examines edge target
+// v of frontier vertex u (when `has`), then the wavefront appends.
+template <class RowT>
+__device__ __forceinline__ void td_visit(const DevG<RowT> &G, int qn, int32_t level, int32_t *dist,
+                                         int32_t *parent, bool has, int32_t u, int32_t v,
+                                         unsigned long long &nfound, unsigned long long &dfound) {
+  bool win = false;
+  int64_t deg = 0;
+  if (has && claim(G.vis, v)) {
+    win = true;
+    dist[v] = level + 1;  // plain store: the claim made this lane the only writer
+    if (parent) parent[v] = u;
+    deg = (int64_t)G.rp[v + 1] - (int64_t)G.rp[v];
+    nfound += 1;
+    dfound += (unsigned long long)deg;
+  }
+  wave_append(G, qn, win, v, deg);
+}
+
+// Top-down, thread per frontier vertex (degree <= t1).  The lanes of a
+// wavefront step through their rows in lock-step so that the append stays
+// wave-converged.
+template <class RowT>
+__global__ void k_td_small(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kTD) return;
+  const int qc = c->qcur, qn = qc ^ 1;
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int64_t cnt = c->qcnt[qc][kSmall];
+  const int32_t *q = qc ? G.qs[1] : G.qs[0];
+  unsigned long long nfound = 0, dfound = 0;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < cnt; base += step) {
+    const int64_t i = base + lane_id();
+    const bool act = i < cnt;
+    const int32_t u = act ? q[i] : 0;
+    const int64_t beg = act ? (int64_t)G.rp[u] : 0;
+    const int64_t end = act ? (int64_t)G.rp[u + 1] : 0;
+    for (int64_t j = beg; __ballot(j < end); ++j) {
+      const bool has = j < end;
+      const int32_t v = has ? G.col[j] : 0;
+      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
+    }
+  }
+  Ctl *cw = G.ctl;
+  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
+}
+
+// Top-down, wavefront per frontier vertex (degree in (t1, t2]): the wave
+// reads the row 64 neighbours at a time (coalesced).
+template <class RowT>
+__global__ void k_td_medium(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kTD) return;
+  const int qc = c->qcur, qn = qc ^ 1;
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int64_t cnt = c->qcnt[qc][kMedium];
+  const int32_t *q = qc ? G.qm[1] : G.qm[0];
+  unsigned long long nfound = 0, dfound = 0;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < cnt; i += waves) {
+    const int32_t u = q[i];
+    const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
+    for (int64_t b = beg; b < end; b += kWave) {
+      const int64_t j = b + lane_id();
+      const bool has = j < end;
+      const int32_t v = has ? G.col[j] : 0;
+      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
+    }
+  }
+  Ctl *cw = G.ctl;
+  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
+}
+
+// Top-down, workgroup per t2-edge chunk of a large frontier vertex.
+template <class RowT>
+__global__ void k_td_large(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kTD) return;
+  const int qc = c->qcur, qn = qc ^ 1;
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int64_t cnt = c->qcnt[qc][kLarge];
+  const uint64_t *q = qc ? G.ql[1] : G.ql[0];
+  unsigned long long nfound = 0, dfound = 0;
+  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const uint64_t e = q[i];
+    const int32_t u = (int32_t)(uint32_t)e;
+    const int64_t chunk = (int64_t)(e >> 32);
+    const int64_t row_end = (int64_t)G.rp[u + 1];
+    const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
+    const int64_t end = min(row_end, beg + (int64_t)G.t2);
+    for (int64_t b = beg + (threadIdx.x & ~63); b < end; b += blockDim.x) {
+      const int64_t j = b + lane_id();
+      const bool has = j < end;
+      const int32_t v = has ? G.col[j] : 0;
+      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
+    }
+  }
+  Ctl *cw = G.ctl;
+  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
+}
+
+// Bottom-up: a wavefront owns 64-bit visited word w (vertices 64w..64w+63).
+template <class RowT>
+__global__ void k_bu(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kBU) return;
+  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
+  uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int lane = lane_id();
+  unsigned long long nfound = 0, dfound = 0, nscan = 0, nexam = 0;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < G.words; w += waves) {
+    const uint64_t vw = G.vis[w];
+    if (vw == ~0ull) {
+      if (lane == 0) next[w] = 0;
+      continue;
+    }
+    const int64_t v = w * kWave + lane;  // ids >= n are marked visited in vw
+    const bool unvisited = !((vw >> lane) & 1ull);
+    bool found = false, heavy = false;
+    int32_t hit = -1;
+    int64_t beg = 0, end = 0, ex = 0;
+    if (unvisited) {
+      beg = (int64_t)G.rp[v];
+      end = (int64_t)G.rp[v + 1];
+      heavy = (end - beg) > G.tbu;
+      if (!heavy) {
+        ex = end - beg;
+        for (int64_t j = beg; j < end; ++j) {
+          const int32_t x = G.col[j];
+          if ((front[x >> 6] >> (x & 63)) & 1ull) {
+            found = true;
+            hit = x;
+            ex = j - beg + 1;
+            break;
+          }
+        }
+      }
+    }
+    // Long rows: the whole wavefront scans one row at a time.
+    uint64_t hm = __ballot(heavy);
+    while (hm) {
+      const int l = __ffsll((unsigned long long)hm) - 1;
+      hm &= hm - 1;
+      const int64_t b0 = __shfl(beg, l), e0 = __shfl(end, l);
+      int64_t exl = e0 - b0;
+      int32_t hitl = -1;
+      for (int64_t b = b0; b < e0; b += kWave) {
+        const int64_t j = b + lane;
+        int32_t x = 0;
+        bool h = false;
+        if (j < e0) {
+          x = G.col[j];
+          h = (front[x >> 6] >> (x & 63)) & 1ull;
+        }
+        const uint64_t hb = __ballot(h);
+        if (hb) {
+          const int f = __ffsll((unsigned long long)hb) - 1;
+          hitl = __shfl(x, f);
+          exl = b - b0 + f + 1;
+          break;
+        }
+      }
+      if (lane == l) {
+        ex = exl;
+        if (hitl >= 0) {
+          found = true;
+          hit = hitl;
+        }
+      }
+    }
+    const uint64_t fm = __ballot(found);
+    if (lane == 0) {
+      next[w] = fm;
+      if (fm) G.vis[w] = vw | fm;
+    }
+    if (found) {
+      dist[v] = level + 1;
+      if (parent) parent[v] = hit;
+      nfound += 1;
+      dfound += (unsigned long long)(end - beg);
+    }
+    nscan += unvisited ? 1 : 0;
+    nexam += (unsigned long long)ex;
+  }
+  Ctl *cw = G.ctl;
+  block_accumulate<4>({nfound, dfound, nscan, nexam},
+                      {&cw->acc_found, &cw->acc_found_deg, &cw->acc_scanned, &cw->acc_examined});
+}
+
+// Level bookkeeping and the direction rule (one thread).
+__global__ void k_decide(Ctl *c, LevelRec *recs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || c->done) return;
+  const int32_t L = c->level;
+  const int32_t cur = c->dir;
+  const int64_t found = (int64_t)c->acc_found;
+  const int64_t fdeg = (int64_t)c->acc_found_deg;
+  if (L < c->rec_cap) {
+    LevelRec r;
+    r.level = L;
+    r.dir = cur;
+    r.n_f = c->n_f;
+    r.m_f = c->m_f;
+    r.m_u = c->m_u;
+    r.found = found;
+    r.scanned = (int64_t)c->acc_scanned;
+    r.examined = (int64_t)c->acc_examined;
+    recs[L] = r;
+  }
+  c->levels_done = L + 1;
+  c->sum_mf += c->m_f;
+  c->reached += found;
+  if (cur == kTD) {
+    // the next frontier was appended to the other queue set; the old set
+    // becomes the target of the following top-down level
+    for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
+    c->qcur ^= 1;
+  } else {
+    c->bcur ^= 1;
+  }
+  c->acc_found = c->acc_found_deg = c->acc_scanned = c->acc_examined = 0;
+  if (found == 0) {
+    c->done = 1;
+    c->conv = kConvNone;
+    return;
+  }
+  const int64_t m_u = c->m_u - fdeg;
+  int32_t nxt;
+  if (c->policy == BFS_POLICY_TD_ONLY) {
+    nxt = kTD;
+  } else if (c->policy == BFS_POLICY_FRONTIER_5PCT) {
+    nxt = (20 * found >= c->n) ? kBU : kTD;
+  } else if (cur == kTD) {
+    nxt = (fdeg * (int64_t)c->alpha > m_u) ? kBU : kTD;
+  } else {
+    nxt = (found * (int64_t)c->beta < c->n && found < c->n_f) ? kTD : kBU;
+  }
+  c->conv = (cur == kTD && nxt == kBU) ? kConvQ2B : (cur == kBU && nxt == kTD) ? kConvB2Q : kConvNone;
+  if (c->conv == kConvB2Q)
+    for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
+  c->n_f = found;
+  c->m_f = fdeg;
+  c->m_u = m_u;
+  c->dir = nxt;
+  c->level = L + 1;
+}
+
+// Queue -> bitmap, step 1: clear the target bitmap.
+template <class RowT>
+__global__ void k_conv_clear(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->conv != kConvQ2B) return;
+  uint64_t *bm = c->bcur ? G.bm[1] : G.bm[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < G.words; w += stride) bm[w] = 0;
+}
+
+// Queue -> bitmap, step 2: set the bit of every frontier vertex.
+template <class RowT>
+__global__ void k_conv_q2b(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->conv != kConvQ2B) return;
+  const int q = c->qcur;
+  uint64_t *bm = c->bcur ? G.bm[1] : G.bm[0];
+  const int64_t c0 = c->qcnt[q][kSmall], c1 = c->qcnt[q][kMedium], c2 = c->qcnt[q][kLarge];
+  const int32_t *qs = q ? G.qs[1] : G.qs[0];
+  const int32_t *qm = q ? G.qm[1] : G.qm[0];
+  const uint64_t *ql = q ? G.ql[1] : G.ql[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c0 + c1 + c2; i += stride) {
+    int32_t v;
+    if (i < c0) {
+      v = qs[i];
+    } else if (i < c0 + c1) {
+      v = qm[i - c0];
+    } else {
+      const uint64_t e = ql[i - c0 - c1];
+      if (e >> 32) continue;  // chunk > 0 of a vertex already counted
+      v = (int32_t)(uint32_t)e;
+    }
+    atomicOr(reinterpret_cast<unsigned long long *>(bm + (v >> 6)), 1ull << (v & 63));
+  }
+}
+
+// Bitmap -> queue: compact the frontier bitmap into degree-bucketed queues
+// (ballot + mbcnt per wavefront, one atomic per wavefront and bucket).
+template <class RowT>
+__global__ void k_conv_b2q(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->conv != kConvB2Q) return;
+  const int qn = c->qcur;
+  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < G.words; w += waves) {
+    const uint64_t word = front[w];
+    if (!word) continue;
+    const int64_t v = w * kWave + lane_id();
+    const bool in = (word >> lane_id()) & 1ull;
+    const int64_t deg = in ? (int64_t)G.rp[v + 1] - (int64_t)G.rp[v] : 0;
+    wave_append(G, qn, in, (int32_t)v, deg);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+inline int blocks_for(int64_t items, int64_t per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+constexpr int kMaxBlocks = 1 << 16;
+
+template <class RowT>
+DevG<RowT> make_devg(bfs_graph *g) {
+  DevG<RowT> G;
+  G.rp = static_cast<const RowT *>(g->rp);
+  G.col = g->col;
+  G.iso = g->iso;
+  G.vis = g->vis;
+  for (int s = 0; s < 2; ++s) {
+    G.bm[s] = g->bm[s];
+    G.qs[s] = g->qs[s];
+    G.qm[s] = g->qm[s];
+    G.ql[s] = g->ql[s];
+  }
+  G.ctl = g->ctl;
+  G.recs = g->recs;
+  G.n = g->n;
+  G.words = g->words;
+  G.t1 = g->params.td_wave_degree;
+  G.t2 = g->params.td_block_degree;
+  G.tbu = g->params.bu_wave_degree;
+  return G;
+}
+
+// Launch shapes shared by both loop drivers.
+struct Shapes {
+  int bs;           // threads per workgroup
+  int wpb;          // wavefronts per workgroup
+  int bu_blocks;    // bottom-up grid
+  int words_blocks; // grid for word-parallel conversions
+};
+
+Shapes shapes_of(const bfs_graph *g) {
+  Shapes s;
+  s.bs = g->params.block_size;
+  s.wpb = s.bs / kWave;
+  s.bu_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
+  s.words_blocks = blocks_for(g->words, s.bs, kMaxBlocks);
+  return s;
+}
+
+template <class RowT>
+int enqueue_conversions(bfs_graph *g, const DevG<RowT> &G, const Shapes &S, hipStream_t st, int conv,
+                        int64_t qentries_bound) {
+  if (conv == kConvQ2B) {
+    hipLaunchKernelGGL(k_conv_clear<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, st, G);
+    hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(qentries_bound, S.bs, kMaxBlocks)),
+                       dim3(S.bs), 0, st, G);
+  } else if (conv == kConvB2Q) {
+    hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, st, G);
+  }
+  BFS_HIP(hipGetLastError());
+  return BFS_OK;
+}
+
+template <class RowT>
+int enqueue_td(const DevG<RowT> &G, const Shapes &S, hipStream_t st, int64_t c0, int64_t c1, int64_t c2) {
+  if (c0 > 0)
+    hipLaunchKernelGGL(k_td_small<RowT>, dim3(blocks_for(c0, S.bs, kMaxBlocks)), dim3(S.bs), 0, st, G);
+  if (c1 > 0)
+    hipLaunchKernelGGL(k_td_medium<RowT>, dim3(blocks_for(c1, S.wpb, kMaxBlocks)), dim3(S.bs), 0, st, G);
+  if (c2 > 0)
+    hipLaunchKernelGGL(k_td_large<RowT>, dim3(blocks_for(c2, 1, kMaxBlocks)), dim3(S.bs), 0, st, G);
+  BFS_HIP(hipGetLastError());
+  return BFS_OK;
+}
+
+int read_ctl(bfs_graph *g, hipStream_t st) {
+  BFS_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  BFS_HIP(hipStreamSynchronize(st));
+  return BFS_OK;
+}
+
+hipEvent_t level_event(bfs_graph *g, size_t i) {
+  while (g->level_events.size() <= i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g->level_events.push_back(e);
+  }
+  return g->level_events[i];
+}
+
+// Host-driven level loop: after every level the 256-byte control block is
+// read back, so each launch is sized to the frontier it processes.
+template <class RowT>
+int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<float> &level_ms) {
+  const Shapes S = shapes_of(g);
+  const bool timing = g->params.collect_timing != 0;
+  int rc;
+  size_t nev = 0;
+  for (;;) {
+    if ((rc = read_ctl(g, st))) return rc;
+    const Ctl h = *g->ctl_host;
+    if (h.done) break;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
+    if ((rc = enqueue_conversions(g, G, S, st, h.conv, qtotal))) return rc;
+    if (timing) {  // the events bracket the level's direction kernels only
+      e0 = level_event(g, nev++);
+      e1 = level_event(g, nev++);
+      if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
+      BFS_HIP(hipEventRecord(e0, st));
+    }
+    if (h.dir == kTD) {
+      int64_t c0 = h.qcnt[h.qcur][0], c1 = h.qcnt[h.qcur][1], c2 = h.qcnt[h.qcur][2];
+      if (h.conv == kConvB2Q) {  // counts are produced on the device by the conversion
+        c0 = c1 = h.n_f;
+        c2 = g->max_degree > G.t2 ? h.m_f / G.t2 + h.n_f : 0;
+      }
+      if ((rc = enqueue_td(G, S, st, c0, c1, c2))) return rc;
+    } else {
+      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, st, G);
+      BFS_HIP(hipGetLastError());
+    }
+    if (timing) BFS_HIP(hipEventRecord(e1, st));
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, st, g->ctl, g->recs);
+    BFS_HIP(hipGetLastError());
+  }
+  if (timing) {
+    level_ms.clear();
+    for (size_t i = 0; i + 1 < nev; i += 2) {
+      float ms = 0.f;
+      BFS_HIP(hipEventElapsedTime(&ms, g->level_events[i], g->level_events[i + 1]));
+      level_ms.push_back(ms);
+    }
+  }
+  return BFS_OK;
+}
+
+// Captured level loop: `K` levels of fixed-shape launches whose kernels read
+// the direction / done flags from the control block; replayed until done.
+template <class RowT>
+int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
+  const Shapes S = shapes_of(g);
+  hipStream_t cs = g->cap_stream;
+  const bool hybrid = policy != BFS_POLICY_TD_ONLY;
+  const bool medium = g->max_degree > G.t1;
+  const bool large = g->max_degree > G.t2;
+  // Fixed grids: enough workgroups to cover the chip several times; the
+  // kernels stride over whatever the control block says.
+  const int td_blocks = blocks_for(g->n, S.bs, 1024);
+  const int med_blocks = blocks_for(g->n, S.wpb, 1024);
+  release_graph_exec(g);
+  BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (int l = 0; l < K; ++l) {
+    if (hybrid) {
+      hipLaunchKernelGGL(k_conv_clear<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, cs, G);
+      hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(g->n, S.bs, 4096)), dim3(S.bs), 0, cs, G);
+      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, cs, G);
+    }
+    hipLaunchKernelGGL(k_td_small<RowT>, dim3(td_blocks), dim3(S.bs), 0, cs, G);
+    if (medium) hipLaunchKernelGGL(k_td_medium<RowT>, dim3(med_blocks), dim3(S.bs), 0, cs, G);
+    if (large) hipLaunchKernelGGL(k_td_large<RowT>, dim3(1024), dim3(S.bs), 0, cs, G);
+    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, cs, G);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, cs, g->ctl, g->recs);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (e != hipSuccess) return fail(BFS_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  g->graph = graph;
+  BFS_HIP(hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
+  g->gexec_levels = K;
+  return BFS_OK;
+}
+
+template <class RowT>
+int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
+  const int K = g->params.graph_chunk_levels;
+  int rc;
+  if (!g->gexec || g->gexec_levels != K) {
+    if ((rc = capture_levels(g, G, policy, K))) return rc;
+  }
+  for (;;) {
+    BFS_HIP(hipGraphLaunch(g->gexec, st));
+    if ((rc = read_ctl(g, st))) return rc;
+    if (g->ctl_host->done) break;
+  }
+  return BFS_OK;
+}
+
+template <class RowT>
+int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const DevG<RowT> G = make_devg<RowT>(g);
+  hipStream_t st = g->stream;
+  const int policy = resolved_policy(g);
+  int loop = g->params.loop;
+  if (loop == BFS_LOOP_AUTO) loop = (policy == BFS_POLICY_TD_ONLY) ? BFS_LOOP_GRAPH : BFS_LOOP_HOST;
+  const int bs = g->params.block_size;
+  BFS_HIP(hipEventRecord(g->ev_start, st));
+  hipLaunchKernelGGL(k_init<RowT>, dim3(blocks_for(std::max(g->n, g->words), bs, 4096)), dim3(bs), 0, st,
+                     G, s, dist, parent, (int32_t)policy, g->params.alpha, g->params.beta, g->nnz,
+                     g->rec_cap);
+  BFS_HIP(hipGetLastError());
+  std::vector<float> level_ms;
+  int rc = (loop == BFS_LOOP_HOST) ? host_loop(g, G, st, level_ms) : graph_loop(g, G, st, policy);
+  if (rc) return rc;
+  BFS_HIP(hipEventRecord(g->ev_stop, st));
+  BFS_HIP(hipEventSynchronize(g->ev_stop));
+  const auto t1 = std::chrono::steady_clock::now();
+  float dev_ms = 0.f;
+  BFS_HIP(hipEventElapsedTime(&dev_ms, g->ev_start, g->ev_stop));
+  const Ctl h = *g->ctl_host;  // final state (read by the loop after the last level)
+  const int nrec = std::min(h.levels_done, g->rec_cap);
+  std::vector<LevelRec> recs(nrec);
+  if (nrec > 0)
+    BFS_HIP(hipMemcpy(recs.data(), g->recs, sizeof(LevelRec) * nrec, hipMemcpyDeviceToHost));
+  g->last_levels.resize(nrec);
+  for (int i = 0; i < nrec; ++i) {
+    bfs_level_stats &o = g->last_levels[i];
+    const LevelRec &r = recs[i];
+    o.level = r.level;
+    o.direction = r.dir;
+    o.frontier = r.n_f;
+    o.frontier_edges = r.m_f;
+    o.unvisited_edges = r.m_u;
+    o.discovered = r.found;
+    o.scanned = r.scanned;
+    o.examined = r.examined;
+    o.ms = i < (int)level_ms.size() ? level_ms[i] : 0.f;
+    o.pad = 0.f;
+  }
+  bfs_run_stats &L = g->last;
+  L.source = s;
+  L.levels = h.levels_done;
+  L.reached = h.reached;
+  L.edges = h.sum_mf / 2;
+  L.device_ms = dev_ms;
+  L.host_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  L.loop = loop;
+  L.policy = policy;
+  return BFS_OK;
+}
+
+}  // namespace
+
+int run_single(bfs_graph *g, int32_t source, int32_t *dist, int32_t *parent) {
+  return g->rp64 ? run_impl<int64_t>(g, source, dist, parent) : run_impl<int32_t>(g, source, dist, parent);
+}
+
+}  // namespace bfsmi

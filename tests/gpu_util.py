@@ -1,0 +1,78 @@
+"""Helpers shared by the GPU tests: run the library, compare with the oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+POLICY_NAMES = {0: "auto", 1: "alpha_beta", 2: "frontier_5pct", 3: "td_only"}
+
+
+def say(*a):
+    """Names the case about to run on the GPU (flushed, so it survives a crash)."""
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def library():
+    import paper_2503_00430_amd as bfs
+    import os
+    if not os.path.exists(bfs.library_path()):
+        from paper_2503_00430_amd import build
+        build.build()
+    bfs.load_library()
+    return bfs
+
+
+def upload(g, flags=0):
+    bfs = library()
+    return bfs.bfs_create_graph(g.row_ptr, g.col_idx, flags)
+
+
+def gpu_bfs(gh, s, parent=True):
+    import torch
+    bfs = library()
+    dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
+    par = torch.empty(gh.n, dtype=torch.int32, device="cuda") if parent else None
+    bfs.bfs_run(gh, int(s), dist, par)
+    return dist.cpu().numpy(), (par.cpu().numpy() if parent else None)
+
+
+def check_single(g, gh, s, *, parent=True, ref=None, full_validate=True, check_levels=True):
+    """Runs one search and checks it against the oracle:
+    dist bit-exact; parents valid; per-level frontier sizes, direction
+    schedule and bottom-up work exactly as the oracle's replay."""
+    bfs = library()
+    d, p = gpu_bfs(gh, s, parent)
+    od = ref if ref is not None else oracle.bfs(g, s, want_parent=False)[0]
+    if not np.array_equal(d, od):
+        bad = np.flatnonzero(d != od)
+        raise AssertionError(f"dist mismatch at {len(bad)} vertices, e.g. v={bad[0]} "
+                             f"gpu={d[bad[0]]} oracle={od[bad[0]]} (source {s})")
+    if full_validate or parent:
+        errs = oracle.validate(g, s, d, p, check_component=full_validate)
+        assert errs == [], errs
+    run, levels = bfs.bfs_get_run_stats(gh)
+    st = oracle.level_stats(g, od)
+    assert run["reached"] == st["reached"]
+    assert run["edges"] == st["m_s"]
+    assert run["levels"] == st["depth"]
+    if check_levels:
+        assert [lv["frontier"] for lv in levels] == st["h"].tolist()
+        assert [lv["frontier_edges"] for lv in levels] == st["mf"].tolist()
+        params = bfs.bfs_get_params(gh)
+        pol = POLICY_NAMES[run["policy"]]
+        sched = oracle.replay_policy(st, pol, params["alpha"], params["beta"])
+        assert [lv["direction"] for lv in levels] == sched, (pol, sched)
+        for lv in levels:
+            L = lv["level"]
+            nxt = int(st["h"][L + 1]) if L + 1 < st["depth"] else 0
+            assert lv["discovered"] == nxt
+            assert lv["unvisited_edges"] == int(st["mu"][L])
+            if lv["direction"] == oracle.BU:
+                prof = oracle.bottom_up_profile(g, od, L)
+                assert lv["scanned"] == prof["unvisited"], (L, lv, prof)
+                assert lv["examined"] == prof["examined"], (L, lv, prof)
+    return d, p, run, levels

@@ -1,0 +1,207 @@
+"""GPU parity of the single-source search (bfs_run) against the oracle.
+
+Distances must be bit-exact; parents must satisfy the BFS-tree invariants
+(they may differ from the oracle's); per-level frontier sizes, the direction
+schedule and the bottom-up work counts must equal the oracle's replay of the
+same switching rule."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import graphs
+from tests.gpu_util import check_single, gpu_bfs, library, say, upload
+
+pytestmark = pytest.mark.gpu
+
+POLICIES = {"alpha_beta": 1, "frontier_5pct": 2, "td_only": 3}
+
+
+@pytest.fixture(scope="module")
+def bfs():
+    return library()
+
+
+@pytest.mark.parametrize("name", sorted(graphs.CLOSED_FORMS))
+@pytest.mark.parametrize("policy", sorted(POLICIES))
+@pytest.mark.parametrize("loop", [1, 2])
+def test_closed_forms(bfs, name, policy, loop):
+    g, f = graphs.CLOSED_FORMS[name]()
+    say("closed form", name, policy, "loop", loop)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, policy=POLICIES[policy], loop=loop, graph_chunk_levels=5)
+    srcs = [0] if name == "binary_tree" else sorted({0, g.n // 3, g.n - 1})
+    for s in srcs:
+        d, _, _, _ = check_single(g, gh, s, ref=f(s).astype(np.int32))
+    gh.close()
+
+
+@pytest.fixture(scope="module")
+def rmat16():
+    return graphgen.rmat(16)
+
+
+def test_rmat16_config(bfs, rmat16):
+    """RMAT scale 16, edge factor 16, int32 row offsets, 16 sources, default
+    (auto = alpha/beta) policy."""
+    g = rmat16
+    say("rmat16 int32 row_ptr, 16 sources")
+    gh = upload(g, bfs.BFS_ROWPTR32)
+    assert bfs.bfs_graph_info_get(gh)["row_ptr_bytes"] == 4
+    for s in graphgen.sources(g, 16):
+        _, _, run, levels = check_single(g, gh, s)
+        assert run["policy"] == bfs.BFS_POLICY_ALPHA_BETA
+    gh.close()
+
+
+@pytest.mark.parametrize("policy", sorted(POLICIES))
+@pytest.mark.parametrize("loop", [1, 2])
+@pytest.mark.parametrize("rp32", [False, True])
+def test_rmat16_policies_loops(bfs, rmat16, policy, loop, rp32):
+    g = rmat16
+    say("rmat16", policy, "loop", loop, "rp32", rp32)
+    gh = upload(g, bfs.BFS_ROWPTR32 if rp32 else 0)
+    bfs.bfs_set_params(gh, policy=POLICIES[policy], loop=loop, graph_chunk_levels=3)
+    for s in graphgen.sources(g, 4, seed=77):
+        check_single(g, gh, s)
+    gh.close()
+
+
+@pytest.mark.parametrize("t1,t2,tbu,bs", [(1, 64, 1, 64), (2, 100, 4, 128), (8, 256, 16, 1024),
+                                          (1000, 100000, 100000, 256), (32, 2048, 64, 512)])
+def test_threshold_sweep(bfs, rmat16, t1, t2, tbu, bs):
+    """Every degree bucket and both bottom-up paths, across workgroup sizes."""
+    g = rmat16
+    say("rmat16 thresholds", t1, t2, tbu, bs)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, td_wave_degree=t1, td_block_degree=t2, bu_wave_degree=tbu, block_size=bs)
+    for pol in (1, 2):
+        bfs.bfs_set_params(gh, policy=pol)
+        for s in graphgen.sources(g, 3, seed=11):
+            check_single(g, gh, s)
+    gh.close()
+
+
+def test_repeat_identical(bfs, rmat16):
+    g = rmat16
+    say("rmat16 repeat x20")
+    gh = upload(g)
+    s = int(graphgen.sources(g, 1)[0])
+    ref, _ = gpu_bfs(gh, s)
+    for _ in range(20):
+        d, p = gpu_bfs(gh, s)
+        assert np.array_equal(d, ref)
+        assert oracle.validate(g, s, d, p, check_component=False) == []
+    gh.close()
+
+
+def test_edge_cases(bfs):
+    say("edge cases")
+    # single vertex
+    g1 = graphgen.from_edges(1, [], [])
+    gh = upload(g1)
+    d, p = gpu_bfs(gh, 0)
+    assert d.tolist() == [0] and p.tolist() == [0]
+    gh.close()
+    # no edges at all, several vertices
+    g0 = graphgen.from_edges(70, [], [])
+    gh = upload(g0)
+    d, p = gpu_bfs(gh, 69)
+    assert d[69] == 0 and (np.delete(d, 69) == -1).all() and p[69] == 69
+    gh.close()
+    # isolated source inside a connected graph
+    g, _ = graphs.path(100)
+    gi = graphgen.from_edges(101, *[np.arange(99), np.arange(1, 100)])
+    gh = upload(gi)
+    check_single(gi, gh, 100)
+    check_single(gi, gh, 0)
+    gh.close()
+    # n not a multiple of 64, last word partly used
+    gr = graphs.random_graph(130, 400, 3)
+    gh = upload(gr)
+    for s in (0, 64, 129):
+        check_single(gr, gh, s)
+    gh.close()
+
+
+@pytest.mark.parametrize("loop", [1, 2])
+def test_hub_chunks(bfs, loop):
+    """A hub of degree 50 000 (far above td_block_degree) as source and as a
+    discovered vertex: its row is split into workgroup chunks."""
+    say("hub chunks loop", loop)
+    k = 50000
+    u = np.concatenate([np.zeros(k, np.int64), np.arange(1, 200)])
+    v = np.concatenate([np.arange(1, k + 1), np.arange(2, 201)])
+    g = graphgen.from_edges(k + 1, u, v)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, loop=loop, policy=3, td_block_degree=1024)
+    for s in (0, 1, 150, k):
+        check_single(g, gh, s)
+    bfs.bfs_set_params(gh, policy=1)
+    for s in (0, 150):
+        check_single(g, gh, s)
+    gh.close()
+
+
+@pytest.mark.parametrize("k", [1, 7, 32, 4096])
+def test_long_path_graph_loop(bfs, k):
+    """Thousands of levels through the captured level loop, chunk sizes that
+    do and do not divide the level count."""
+    say("path 3000, graph chunk", k)
+    g, f = graphs.path(3000)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, loop=2, policy=3, graph_chunk_levels=k)
+    check_single(g, gh, 0, ref=f(0).astype(np.int32))
+    check_single(g, gh, 1500, ref=f(1500).astype(np.int32))
+    gh.close()
+
+
+def test_device_input(bfs, rmat16):
+    import torch
+    g = rmat16
+    say("device-resident CSR input")
+    rp = torch.from_numpy(g.row_ptr.copy()).cuda()
+    col = torch.from_numpy(g.col_idx.copy()).cuda()
+    gh = bfs.bfs_create_graph(rp, col, bfs.BFS_VALIDATE)
+    check_single(g, gh, int(graphgen.sources(g, 1)[0]))
+    gh.close()
+
+
+def test_validate_flags(bfs):
+    say("create-time validation")
+    rp = np.array([0, 1, 1], np.int64)
+    col = np.array([1], np.int32)  # 0->1 without 1->0
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_create_graph(rp, col, bfs.BFS_VALIDATE | bfs.BFS_VALIDATE_SYMMETRY)
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_create_graph(np.array([0, 1, 2], np.int64), np.array([1, 5], np.int32), bfs.BFS_VALIDATE)
+    gh = bfs.bfs_create_graph(np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32),
+                              bfs.BFS_VALIDATE | bfs.BFS_VALIDATE_SYMMETRY)
+    import torch
+    d = torch.empty(2, dtype=torch.int32, device="cuda")
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_run(gh, 2, d)
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_set_params(gh, block_size=100)
+    gh.close()
+
+
+def test_grid_small_many_sources(bfs):
+    """512 x 512 perturbed lattice (average degree 3.6 => auto picks top-down
+    only and the captured level loop)."""
+    g = graphgen.grid(512)
+    say("grid512, 8 sources")
+    gh = upload(g)
+    for s in graphgen.sources(g, 8):
+        _, _, run, _ = check_single(g, gh, s)
+        assert run["policy"] == 3 and run["loop"] == 2
+    gh.close()
+
+
+def test_urand(bfs):
+    g = graphgen.urand(1 << 16, 16)
+    say("urand 2^16 d16")
+    gh = upload(g)
+    for s in graphgen.sources(g, 4):
+        check_single(g, gh, s)
+    gh.close()
