@@ -1,8 +1,319 @@
-// Batched multi-source BFS (placeholder until the persistent kernel lands).
+// Batched multi-source BFS: up to 64 searches share one traversal.
+//
+// Every vertex carries three 64-bit sets, bit i standing for search i:
+//   seen[v]  - searches that have reached v,
+//   front[v] - searches for which v is on the current frontier,
+//   next[v]  - candidate bits gathered during the running level.
+// A level is the level-synchronous step of the single-source search
+// (Section 2, Listing 1) applied to all searches at once:
+//   top-down  - each vertex with front[v] != 0 pushes front[v] & ~seen[n]
+//               into next[n] of every neighbour n (atomicOr on the word);
+//   bottom-up - each vertex with unfinished searches ORs the front sets of
+//               its neighbours, stopping as soon as every search it still
+//               lacks has been found (the early exit of Section 2,
+//               BFS-Hybrid, extended to 64 searches);
+// then a finalize pass turns next into the new frontier, marks it seen and
+// writes the level into the uint8 distance rows.  The direction of each
+// level follows the frontier's edge count.
+//
+// The whole search is one cooperative launch: levels are separated by
+// grid-wide barriers, and a single thread decides the next direction and
+// termination from counters reduced on the device.
+
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "common.h"
 
+namespace cg = cooperative_groups;
+
 namespace bfsmi {
-int run_batch(bfs_graph *, const int32_t *, int32_t, uint8_t *, hipStream_t) {
-  return fail(BFS_ERR_DEVICE, "bfs_run_batch is not available in this build");
+namespace {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
 }
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+  return x;
+}
+
+// Device control block of one batched search.
+struct MsCtl {
+  int32_t dir;    // 0 top-down, 1 bottom-up
+  int32_t done;
+  int32_t levels;
+  int32_t pad;
+  unsigned long long alive;  // searches whose frontier is not empty
+  unsigned long long acc[2][3];  // per level parity: new pairs, frontier edges, OR of new bits
+  int32_t src[64];
+};
+
+template <class RowT>
+struct MsArgs {
+  const RowT *rp;
+  const int32_t *col;
+  int64_t n, nnz;
+  uint64_t *seen, *front, *next;
+  uint8_t *dist8;
+  MsCtl *ctl;
+  int32_t k;
+  int32_t bu_percent;
+  int32_t heavy;  // rows longer than this are handled by the whole wavefront
+  int32_t aligned4;  // dist8 is 4-byte aligned
+};
+
+// Top-down expansion of the wavefront's 64 vertices starting at v0.
+template <class RowT>
+__device__ void ms_td(const MsArgs<RowT> &A, int64_t v0) {
+  const int lane = lane_id();
+  const int64_t v = v0 + lane;
+  const uint64_t f = v < A.n ? A.front[v] : 0ull;
+  int64_t beg = 0, end = 0;
+  if (f) {
+    beg = (int64_t)A.rp[v];
+    end = (int64_t)A.rp[v + 1];
+  }
+  const bool heavy = (end - beg) > A.heavy;
+  if (f && !heavy) {
+    for (int64_t j = beg; j < end; ++j) {
+      const int32_t x = A.col[j];
+      const uint64_t nb = f & ~A.seen[x];
+      if (nb) atomicOr(reinterpret_cast<unsigned long long *>(A.next + x), (unsigned long long)nb);
+    }
+  }
+  uint64_t hm = __ballot(heavy);
+  while (hm) {
+    const int l = __ffsll((unsigned long long)hm) - 1;
+    hm &= hm - 1;
+    const int64_t b0 = __shfl(beg, l), e0 = __shfl(end, l);
+    const uint64_t fl = __shfl(f, l);
+    for (int64_t j = b0 + lane; j < e0; j += kWave) {
+      const int32_t x = A.col[j];
+      const uint64_t nb = fl & ~A.seen[x];
+      if (nb) atomicOr(reinterpret_cast<unsigned long long *>(A.next + x), (unsigned long long)nb);
+    }
+  }
+}
+
+// Bottom-up gathering for the wavefront's 64 vertices starting at v0.
+template <class RowT>
+__device__ void ms_bu(const MsArgs<RowT> &A, int64_t v0, uint64_t alive) {
+  const int lane = lane_id();
+  const int64_t v = v0 + lane;
+  const uint64_t target = v < A.n ? (~A.seen[v] & alive) : 0ull;
+  int64_t beg = 0, end = 0;
+  if (target) {
+    beg = (int64_t)A.rp[v];
+    end = (int64_t)A.rp[v + 1];
+  }
+  const bool heavy = (end - beg) > A.heavy;
+  uint64_t acc = 0;
+  if (target && !heavy) {
+    for (int64_t j = beg; j < end; ++j) {
+      acc |= A.front[A.col[j]];
+      if ((acc & target) == target) break;
+    }
+  }
+  uint64_t hm = __ballot(heavy);
+  while (hm) {
+    const int l = __ffsll((unsigned long long)hm) - 1;
+    hm &= hm - 1;
+    const int64_t b0 = __shfl(beg, l), e0 = __shfl(end, l);
+    const uint64_t tl = __shfl(target, l);
+    uint64_t al = 0;
+    for (int64_t b = b0; b < e0; b += kWave) {
+      const int64_t j = b + lane;
+      const uint64_t fr = j < e0 ? A.front[A.col[j]] : 0ull;
+      al |= wave_or(fr);
+      if ((al & tl) == tl) break;
+    }
+    if (lane == l) acc = al;
+  }
+  if (v < A.n) A.next[v] = acc & target;
+}
+
+template <class RowT>
+__global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
+  cg::grid_group grid = cg::this_grid();
+  const int lane = lane_id();
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t wave = tid >> 6;
+  const int64_t nwaves = nthreads >> 6;
+  const int64_t nwords = (A.n + kWave - 1) / kWave;
+  MsCtl *c = A.ctl;
+  __shared__ unsigned long long part[3][16];
+
+  // Initialisation: empty sets, every distance 255 (unreached).
+  for (int64_t v = tid; v < A.n; v += nthreads) {
+    A.seen[v] = 0;
+    A.front[v] = 0;
+    A.next[v] = 0;
+  }
+  const int64_t bytes = (int64_t)A.k * A.n;
+  const int64_t head = A.aligned4 ? bytes / 4 : 0;  // 4-byte stores when the rows allow it
+  uint32_t *d32 = reinterpret_cast<uint32_t *>(A.dist8);
+  for (int64_t i = tid; i < head; i += nthreads) d32[i] = 0xFFFFFFFFu;
+  for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) A.dist8[i] = 255;
+  if (tid == 0) {
+    c->dir = 0;
+    c->done = 0;
+    c->levels = 0;
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 3; ++q) c->acc[p][q] = 0;
+    c->alive = A.k == 64 ? ~0ull : ((1ull << A.k) - 1);
+  }
+  grid.sync();
+  if (tid < A.k) {
+    const int32_t s = c->src[tid];
+    const unsigned long long bit = 1ull << tid;
+    atomicOr(reinterpret_cast<unsigned long long *>(A.seen + s), bit);
+    atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
+    A.dist8[(int64_t)tid * A.n + s] = 0;
+  }
+  grid.sync();
+
+  for (int64_t level = 0; level <= A.n; ++level) {
+    const int32_t dir = __atomic_load_n(&c->dir, __ATOMIC_RELAXED);
+    const uint64_t alive = __atomic_load_n(&c->alive, __ATOMIC_RELAXED);
+    for (int64_t w = wave; w < nwords; w += nwaves) {
+      if (dir == 0)
+        ms_td(A, w * kWave);
+      else
+        ms_bu(A, w * kWave, alive);
+    }
+    grid.sync();
+    // Finalize: next -> new frontier, seen, distance rows.
+    const uint8_t dval = (uint8_t)(level + 1 < 255 ? level + 1 : 255);
+    unsigned long long pairs = 0, fedges = 0, bits = 0;
+    for (int64_t w = wave; w < nwords; w += nwaves) {
+      const int64_t v = w * kWave + lane;
+      uint64_t nb = 0;
+      if (v < A.n) {
+        const uint64_t s = A.seen[v];
+        nb = A.next[v] & ~s;
+        A.next[v] = 0;
+        A.front[v] = nb;
+        if (nb) {
+          A.seen[v] = s | nb;
+          pairs += (unsigned long long)__popcll(nb);
+          fedges += (unsigned long long)((int64_t)A.rp[v + 1] - (int64_t)A.rp[v]);
+          bits |= nb;
+        }
+      }
+      uint64_t any = wave_or(nb);
+      while (any) {  // one coalesced byte row segment per search that advanced
+        const int i = __ffsll((unsigned long long)any) - 1;
+        any &= any - 1;
+        if ((nb >> i) & 1ull) A.dist8[(int64_t)i * A.n + v] = dval;
+      }
+    }
+    pairs = wave_sum(pairs);
+    fedges = wave_sum(fedges);
+    bits = wave_or(bits);
+    if (lane == 0) {
+      part[0][threadIdx.x >> 6] = pairs;
+      part[1][threadIdx.x >> 6] = fedges;
+      part[2][threadIdx.x >> 6] = bits;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long p = 0, fe = 0, b = 0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        p += part[0][i];
+        fe += part[1][i];
+        b |= part[2][i];
+      }
+      const int par = (int)(level & 1);
+      if (p) atomicAdd(&c->acc[par][0], p);
+      if (fe) atomicAdd(&c->acc[par][1], fe);
+      if (b) atomicOr(&c->acc[par][2], b);
+    }
+    grid.sync();
+    if (tid == 0) {
+      const int par = (int)(level & 1);
+      const unsigned long long p = c->acc[par][0], fe = c->acc[par][1];
+      c->alive = c->acc[par][2];
+      c->levels = (int32_t)(level + 1);
+      if (p == 0) {
+        c->done = 1;
+      } else {
+        c->dir = (fe * 100ull > (unsigned long long)A.bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
+      }
+      for (int q = 0; q < 3; ++q) c->acc[par ^ 1][q] = 0;
+    }
+    grid.sync();
+    if (__atomic_load_n(&c->done, __ATOMIC_RELAXED)) break;
+  }
+}
+
+int ensure_ms_scratch(bfs_graph *g) {
+  if (g->ms.seen) return BFS_OK;
+  const size_t words = (size_t)g->n;
+  void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+  const size_t sizes[4] = {words * 8, words * 8, words * 8, sizeof(MsCtl)};
+  for (int i = 0; i < 4; ++i) {
+    if (hipMalloc(&p[i], sizes[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+      return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate batched-search scratch");
+    }
+  }
+  g->ms.seen = static_cast<uint64_t *>(p[0]);
+  g->ms.front = static_cast<uint64_t *>(p[1]);
+  g->ms.next = static_cast<uint64_t *>(p[2]);
+  g->ms.counters = static_cast<unsigned long long *>(p[3]);
+  g->ms.bytes = sizes[0] + sizes[1] + sizes[2] + sizes[3];
+  return BFS_OK;
+}
+
+template <class RowT>
+int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t st) {
+  int rc = ensure_ms_scratch(g);
+  if (rc) return rc;
+  MsArgs<RowT> A;
+  A.rp = static_cast<const RowT *>(g->rp);
+  A.col = g->col;
+  A.n = g->n;
+  A.nnz = g->nnz;
+  A.seen = g->ms.seen;
+  A.front = g->ms.front;
+  A.next = g->ms.next;
+  A.dist8 = dist8;
+  A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
+  A.k = k;
+  A.bu_percent = g->params.msbfs_bu_percent;
+  A.heavy = kWave;
+  A.aligned4 = (reinterpret_cast<uintptr_t>(dist8) & 3) == 0;
+  // sources go straight into the control block
+  BFS_HIP(hipMemcpyAsync(reinterpret_cast<char *>(A.ctl) + offsetof(MsCtl, src), sources,
+                         sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+  const int bs = g->params.msbfs_block_size;
+  int per_cu = 0, cus = 0;
+  BFS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_msbfs<RowT>, bs, 0));
+  BFS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  if (per_cu < 1) return fail(BFS_ERR_DEVICE, "batched kernel cannot be resident");
+  const int blocks = per_cu * cus;
+  void *args[] = {&A};
+  BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_msbfs<RowT>), dim3(blocks),
+                                     dim3(bs), args, 0, st));
+  BFS_HIP(hipStreamSynchronize(st));
+  return BFS_OK;
+}
+
+}  // namespace
+
+int run_batch(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t stream) {
+  hipStream_t st = stream ? stream : g->stream;
+  return g->rp64 ? batch_impl<int64_t>(g, sources, k, dist8, st)
+                 : batch_impl<int32_t>(g, sources, k, dist8, st);
+}
+
 }  // namespace bfsmi

@@ -1,0 +1,137 @@
+"""GPU parity of the batched multi-source search (bfs_run_batch): every row
+of the uint8 [k][N] output must equal min(oracle distance, 255), with 255
+for unreached vertices."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import graphs
+from tests.gpu_util import library, say, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bfs():
+    return library()
+
+
+def run_batch(bfs, gh, sources):
+    import torch
+    out = torch.empty((len(sources), gh.n), dtype=torch.uint8, device="cuda")
+    bfs.bfs_run_batch(gh, np.asarray(sources, np.int32), out)
+    return out.cpu().numpy()
+
+
+def expect(g, sources):
+    return oracle.msbfs_dist8(g, [int(s) for s in sources])
+
+
+@pytest.fixture(scope="module")
+def rmat16():
+    return graphgen.rmat(16)
+
+
+@pytest.mark.parametrize("k", [1, 2, 63, 64])
+def test_rmat16_batches(bfs, rmat16, k):
+    g = rmat16
+    say("batch rmat16 k", k)
+    gh = upload(g)
+    srcs = graphgen.sources(g, k, seed=900 + k)
+    got = run_batch(bfs, gh, srcs)
+    np.testing.assert_array_equal(got, expect(g, srcs))
+    gh.close()
+
+
+@pytest.mark.parametrize("pct", [0, 1, 5, 30, 100])
+def test_direction_thresholds(bfs, rmat16, pct):
+    g = rmat16
+    say("batch rmat16 bu_percent", pct)
+    gh = upload(g, bfs.BFS_ROWPTR32)
+    bfs.bfs_set_params(gh, msbfs_bu_percent=pct)
+    srcs = graphgen.sources(g, 64, seed=31)
+    np.testing.assert_array_equal(run_batch(bfs, gh, srcs), expect(g, srcs))
+    gh.close()
+
+
+def test_duplicates_isolated_and_components(bfs):
+    say("batch duplicates / isolated / components")
+    g = graphgen.from_edges(200, np.concatenate([np.arange(99), 100 + np.arange(80)]),
+                            np.concatenate([np.arange(1, 100), 101 + np.arange(80)]))
+    gh = upload(g)
+    srcs = [0, 0, 50, 199, 150, 99, 100, 180, 50]  # repeats; 199 isolated
+    np.testing.assert_array_equal(run_batch(bfs, gh, srcs), expect(g, srcs))
+    gh.close()
+
+
+def test_saturation_long_path(bfs):
+    say("batch path 700 saturation")
+    g, _ = graphs.path(700)
+    gh = upload(g)
+    srcs = [0, 699, 350, 10]
+    got = run_batch(bfs, gh, srcs)
+    np.testing.assert_array_equal(got, expect(g, srcs))
+    assert got[0, 254] == 254 and got[0, 255] == 255 and got[0, 699] == 255
+    gh.close()
+
+
+def test_closed_forms(bfs):
+    for name, mk in sorted(graphs.CLOSED_FORMS.items()):
+        g, f = mk()
+        say("batch closed form", name)
+        gh = upload(g)
+        srcs = [0] if name == "binary_tree" else list(range(0, g.n, max(1, g.n // 20)))[:64]
+        got = run_batch(bfs, gh, srcs)
+        for i, s in enumerate(srcs):
+            d = f(s)
+            np.testing.assert_array_equal(got[i], np.where((d < 0) | (d >= 255), 255, d))
+        gh.close()
+
+
+def test_hub_rows(bfs):
+    """Rows far longer than a wavefront, in both directions."""
+    say("batch hub rows")
+    k = 20000
+    u = np.concatenate([np.zeros(k, np.int64), np.arange(1, 300), [5000] * 3000])
+    v = np.concatenate([np.arange(1, k + 1), np.arange(2, 301), np.arange(10000, 13000)])
+    g = graphgen.from_edges(k + 1, u, v)
+    gh = upload(g)
+    for pct in (0, 100):
+        bfs.bfs_set_params(gh, msbfs_bu_percent=pct)
+        srcs = [0, 1, 150, 5000, 12000, k]
+        np.testing.assert_array_equal(run_batch(bfs, gh, srcs), expect(g, srcs))
+    gh.close()
+
+
+def test_bad_arguments(bfs, rmat16):
+    import torch
+    gh = upload(rmat16)
+    out = torch.empty((65, gh.n), dtype=torch.uint8, device="cuda")
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_run_batch(gh, np.arange(65, dtype=np.int32), out)
+    out1 = torch.empty((1, gh.n), dtype=torch.uint8, device="cuda")
+    with pytest.raises(bfs.BfsError):
+        bfs.bfs_run_batch(gh, np.array([gh.n], np.int32), out1)
+    gh.close()
+
+
+def test_rmat22_config(bfs):
+    """RMAT scale 22, 64 sources in one launch: 8 rows against the oracle in
+    full, every row's reached count against its source's component."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    say("generating rmat22")
+    g = graphgen.rmat(22)
+    gh = upload(g)
+    srcs = graphgen.sources(g, 64)
+    say("batch rmat22 k=64")
+    got = run_batch(bfs, gh, srcs)
+    pick = list(range(0, 64, 8))
+    np.testing.assert_array_equal(got[pick], expect(g, srcs[pick]))
+    a = csr_matrix((np.ones(g.nnz, np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    _, lab = connected_components(a, directed=False)
+    sizes = np.bincount(lab)
+    for i, s in enumerate(srcs):
+        assert int((got[i] != 255).sum()) == sizes[lab[s]]
+    gh.close()
