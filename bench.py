@@ -100,6 +100,59 @@ def cpu_baseline(g, sources, budget_s=20.0, max_sources=8):
                       f"serial FIFO BFS with parents, {t_total:.1f} s of CPU time"}
 
 
+def bench_batched(bfs, torch, reps=3):
+    """RMAT scale 22, 64 sources: one bfs_run_batch against 64 bfs_run calls."""
+    g, sources, _ = make_graph("rmat22")
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx)
+    out8 = torch.empty((len(sources), g.n), dtype=torch.uint8, device="cuda")
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    bfs.bfs_run_batch(gh, sources, out8)  # warm-up
+    edges, plain = {}, []
+    for _ in range(reps):
+        tot = 0.0
+        for s in sources:
+            bfs.bfs_run(gh, int(s), dist)
+            run, _ = bfs.bfs_get_run_stats(gh)
+            edges[int(s)] = run["edges"]
+            tot += run["host_ms"]
+        plain.append(tot)
+    batch = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bfs.bfs_run_batch(gh, sources, out8)
+        batch.append((time.perf_counter() - t0) * 1e3)
+    m = sum(edges.values())
+    tb, tp = statistics.median(batch), statistics.median(plain)
+    gh.close()
+    return {"workload": "rmat22_ef16_64src", "n": g.n, "nnz": g.nnz, "batch_ms": round(tb, 3),
+            "plain_64_ms": round(tp, 3), "batch_gteps": round(m / tb / 1e6, 3),
+            "plain_gteps": round(m / tp / 1e6, 3), "speedup": round(tp / tb, 3)}
+
+
+def bench_mesh(bfs, torch, reps=2):
+    """4096 x 4096 perturbed lattice, 16 sources (top-down only, captured loop)."""
+    g, sources, _ = make_graph("grid4096")
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    bfs.bfs_run(gh, int(sources[0]), dist)  # warm-up (captures the level loop)
+    per = {}
+    levels = []
+    for _ in range(reps):
+        for s in sources:
+            bfs.bfs_run(gh, int(s), dist)
+            run, _ = bfs.bfs_get_run_stats(gh)
+            per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
+            levels.append(run["levels"])
+    teps = [e / statistics.median(t) for e, t in per.values()]
+    gh.close()
+    hm = len(teps) / sum(1.0 / t for t in teps) / 1e9
+    mean_ms = statistics.mean(statistics.median(t) for _, t in per.values()) * 1e3
+    return {"workload": "grid4096_p0.1_16src", "n": g.n, "nnz": g.nnz, "gteps_hm": round(hm, 4),
+            "ms_per_bfs": round(mean_ms, 3), "levels_mean": round(statistics.mean(levels), 1),
+            "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and mesh sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -176,6 +230,14 @@ def main():
                     "traffic": measured_traffic(args.workload), "kernel": "k_bu",
                     "avg_launch_us": round(avg_s * 1e6, 2),
                     "algo_bytes_per_launch": int(avg_bytes), "launches": len(bu_levels)}
+    # per-level profile of the first source (stderr, for reading)
+    s0, run0, lvs0 = records[0]
+    log(f"source {s0}: {run0['levels']} levels, host {run0['host_ms']:.3f} ms, "
+        f"device {run0['device_ms']:.3f} ms")
+    for lv in lvs0:
+        log(f"  L{lv['level']:<3d} {'TB'[lv['direction']]} n_f={lv['frontier']:<9d} "
+            f"m_f={lv['frontier_edges']:<10d} found={lv['discovered']:<9d} "
+            f"scanned={lv['scanned']:<9d} examined={lv['examined']:<10d} {lv['ms'] * 1e3:9.1f} us")
     schedules = {}
     for _, _, lvs in records[: len(sources)]:
         key = "".join("TB"[lv["direction"]] for lv in lvs)
@@ -207,6 +269,13 @@ def main():
     gh.close()
     del dist, parent
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("batched section (rmat22)")
+        out["batched"] = bench_batched(bfs, torch)
+        torch.cuda.empty_cache()
+        log("mesh section (grid4096)")
+        out["mesh"] = bench_mesh(bfs, torch)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, sources)

@@ -86,7 +86,7 @@ typedef struct bfs_params {
                                  td_block_degree-edge chunk (default 2048) */
   int32_t bu_wave_degree;     /* bottom-up: unvisited vertices with degree > this are
                                  scanned by the whole wavefront (default 64) */
-  int32_t block_size;         /* threads per workgroup for vertex-parallel kernels (default 256) */
+  int32_t block_size;         /* threads per workgroup of the level kernels (default 512) */
   int32_t loop;               /* bfs_loop */
   int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 32) */
   int32_t collect_timing;     /* nonzero: time each level with HIP events (HOST loop) */

@@ -97,7 +97,7 @@ static void destroy(bfs_graph *g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   release_graph_exec(g);
   void *ptrs[] = {g->rp, g->col, g->iso, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
-                  g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->ctl, g->recs,
+                  g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->ctl, g->recs, g->partials,
                   g->ms.seen, g->ms.front, g->ms.next, g->ms.counters};
   for (void *p : ptrs) free_dev(p);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
@@ -143,7 +143,7 @@ static bfs_params default_params() {
   p.td_wave_degree = 32;
   p.td_block_degree = 2048;
   p.bu_wave_degree = 64;
-  p.block_size = 256;
+  p.block_size = 512;
   p.loop = BFS_LOOP_AUTO;
   p.graph_chunk_levels = 32;
   p.collect_timing = 0;
@@ -284,6 +284,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     ALLOC(g->qm[s], n);
   }
   ALLOC(g->ctl, 1);
+  ALLOC(g->partials, (size_t)kMaxBlocks * kPartials);
   g->rec_cap = 1 << 16;
   ALLOC(g->recs, g->rec_cap);
 #undef ALLOC
@@ -306,6 +307,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   if (e == hipSuccess && nnz > 0) e = hipMemcpy(g->col, col_idx, sizeof(int32_t) * nnz, kind);
   if (e == hipSuccess) e = hipMemcpy(g->iso, iso.data(), sizeof(uint64_t) * g->words, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(g->ctl, 0, sizeof(Ctl));
+  if (e == hipSuccess) e = hipMemset(g->partials, 0, sizeof(unsigned long long) * kMaxBlocks * kPartials);
   if (e == hipSuccess) e = hipEventCreate(&g->ev_start);
   if (e == hipSuccess) e = hipEventCreate(&g->ev_stop);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);

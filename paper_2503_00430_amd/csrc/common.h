@@ -27,10 +27,10 @@ struct LevelRec {
 };
 
 // Device-resident control block of one single-source search.  The level
-// state is written only by the single-thread decide step (and by the init
-// kernel); the accumulators are added to by the level kernels and cleared by
-// decide.  Every kernel reads what it needs from here, so a captured
-// sequence of kernels stays valid from level to level.
+// state is written only by the decide step (and by the init kernel); the
+// level kernels add only to the queue counts.  Every kernel reads what it
+// needs from here, so a captured sequence of kernels stays valid from level
+// to level.
 struct alignas(256) Ctl {
   int32_t level;   // level about to run: expands vertices at distance `level`
   int32_t dir;     // its direction (kTD / kBU)
@@ -51,13 +51,16 @@ struct alignas(256) Ctl {
   int64_t reached;  // vertices visited so far
   unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
   unsigned int pad1[2];
-  unsigned long long acc_found;     // vertices discovered by the running level
-  unsigned long long acc_found_deg; // sum of their degrees
-  unsigned long long acc_scanned;   // bottom-up: unvisited vertices examined
-  unsigned long long acc_examined;  // bottom-up: neighbours examined
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
 };
+
+// Level kernels run at most kMaxBlocks workgroups; each writes its counts
+// (found, degree sum of found, scanned, examined) to its own slot of the
+// partials array, which the decide step reduces and clears.  No two
+// workgroups add to the same device word.
+constexpr int kMaxBlocks = 1024;
+constexpr int kPartials = 4;
 
 // Everything a single-source kernel needs, passed by value.
 template <class RowT>
@@ -72,6 +75,7 @@ struct DevG {
   uint64_t *ql[2];      //             large-degree vertices, one entry per chunk: chunk << 32 | v
   Ctl *ctl;
   LevelRec *recs;
+  unsigned long long *partials;  // [kMaxBlocks][kPartials]
   int64_t n;
   int64_t words;        // 64-bit words per bitmap
   int32_t t1, t2, tbu;  // degree thresholds (td_wave_degree, td_block_degree, bu_wave_degree)
@@ -102,6 +106,7 @@ struct bfs_graph {
   int64_t ql_cap = 0;
   bfsmi::Ctl *ctl = nullptr;
   bfsmi::Ctl *ctl_host = nullptr;  // pinned mirror
+  unsigned long long *partials = nullptr;
   bfsmi::LevelRec *recs = nullptr;
   int32_t rec_cap = 0;
   int64_t isolated = 0, max_degree = 0;

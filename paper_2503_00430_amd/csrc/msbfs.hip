@@ -52,9 +52,12 @@ struct MsCtl {
   int32_t levels;
   int32_t pad;
   unsigned long long alive;  // searches whose frontier is not empty
-  unsigned long long acc[2][3];  // per level parity: new pairs, frontier edges, OR of new bits
   int32_t src[64];
 };
+
+constexpr size_t kMsCtlBytes = 1024;  // MsCtl, rounded up
+constexpr int kMsMaxBlocks = 8192;
+static_assert(sizeof(MsCtl) <= kMsCtlBytes, "control block too large");
 
 template <class RowT>
 struct MsArgs {
@@ -64,6 +67,7 @@ struct MsArgs {
   uint64_t *seen, *front, *next;
   uint8_t *dist8;
   MsCtl *ctl;
+  unsigned long long *partials;  // [grid][3]: new pairs, frontier edges, OR of new bits
   int32_t k;
   int32_t bu_percent;
   int32_t heavy;  // rows longer than this are handled by the whole wavefront
@@ -167,8 +171,6 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     c->dir = 0;
     c->done = 0;
     c->levels = 0;
-    for (int p = 0; p < 2; ++p)
-      for (int q = 0; q < 3; ++q) c->acc[p][q] = 0;
     c->alive = A.k == 64 ? ~0ull : ((1ull << A.k) - 1);
   }
   grid.sync();
@@ -225,30 +227,49 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
       part[2][threadIdx.x >> 6] = bits;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {  // this workgroup's totals, in its own slot
       unsigned long long p = 0, fe = 0, b = 0;
       for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
         p += part[0][i];
         fe += part[1][i];
         b |= part[2][i];
       }
-      const int par = (int)(level & 1);
-      if (p) atomicAdd(&c->acc[par][0], p);
-      if (fe) atomicAdd(&c->acc[par][1], fe);
-      if (b) atomicOr(&c->acc[par][2], b);
+      A.partials[(size_t)blockIdx.x * 3 + 0] = p;
+      A.partials[(size_t)blockIdx.x * 3 + 1] = fe;
+      A.partials[(size_t)blockIdx.x * 3 + 2] = b;
     }
     grid.sync();
-    if (tid == 0) {
-      const int par = (int)(level & 1);
-      const unsigned long long p = c->acc[par][0], fe = c->acc[par][1];
-      c->alive = c->acc[par][2];
-      c->levels = (int32_t)(level + 1);
-      if (p == 0) {
-        c->done = 1;
-      } else {
-        c->dir = (fe * 100ull > (unsigned long long)A.bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
+    if (blockIdx.x == 0) {  // workgroup 0 reduces the slots and decides
+      unsigned long long p = 0, fe = 0, b = 0;
+      for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        p += A.partials[(size_t)i * 3 + 0];
+        fe += A.partials[(size_t)i * 3 + 1];
+        b |= A.partials[(size_t)i * 3 + 2];
       }
-      for (int q = 0; q < 3; ++q) c->acc[par ^ 1][q] = 0;
+      p = wave_sum(p);
+      fe = wave_sum(fe);
+      b = wave_or(b);
+      __syncthreads();  // `part` is reused
+      if (lane == 0) {
+        part[0][threadIdx.x >> 6] = p;
+        part[1][threadIdx.x >> 6] = fe;
+        part[2][threadIdx.x >> 6] = b;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        unsigned long long tp = 0, tf = 0, tb = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+          tp += part[0][i];
+          tf += part[1][i];
+          tb |= part[2][i];
+        }
+        c->alive = tb;
+        c->levels = (int32_t)(level + 1);
+        if (tp == 0)
+          c->done = 1;
+        else
+          c->dir = (tf * 100ull > (unsigned long long)A.bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
+      }
     }
     grid.sync();
     if (__atomic_load_n(&c->done, __ATOMIC_RELAXED)) break;
@@ -259,7 +280,7 @@ int ensure_ms_scratch(bfs_graph *g) {
   if (g->ms.seen) return BFS_OK;
   const size_t words = (size_t)g->n;
   void *p[4] = {nullptr, nullptr, nullptr, nullptr};
-  const size_t sizes[4] = {words * 8, words * 8, words * 8, sizeof(MsCtl)};
+  const size_t sizes[4] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8};
   for (int i = 0; i < 4; ++i) {
     if (hipMalloc(&p[i], sizes[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
@@ -288,6 +309,7 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   A.next = g->ms.next;
   A.dist8 = dist8;
   A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
+  A.partials = g->ms.counters + kMsCtlBytes / 8;
   A.k = k;
   A.bu_percent = g->params.msbfs_bu_percent;
   A.heavy = kWave;
@@ -300,7 +322,7 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   BFS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_msbfs<RowT>, bs, 0));
   BFS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   if (per_cu < 1) return fail(BFS_ERR_DEVICE, "batched kernel cannot be resident");
-  const int blocks = per_cu * cus;
+  const int blocks = std::min(per_cu * cus, kMsMaxBlocks);
   void *args[] = {&A};
   BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_msbfs<RowT>), dim3(blocks),
                                      dim3(bs), args, 0, st));

@@ -60,11 +60,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
   return x;
 }
 
-// Adds the workgroup totals of K per-thread counters to K device counters
-// (one atomic per workgroup and counter).  Every thread of the workgroup
-// must call it.
-template <int K>
-__device__ void block_accumulate(const unsigned long long (&v)[K], unsigned long long *const (&dst)[K]) {
+// Writes the workgroup totals of K per-thread counters to this workgroup's
+// slot of the partials array (plain stores; the decide step reduces them).
+// Every thread of the workgroup must call it.
+template <int K, class RowT>
+__device__ __forceinline__ void block_partials(const DevG<RowT> &G, const unsigned long long (&v)[K]) {
   __shared__ unsigned long long part[K][16];
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -77,7 +77,7 @@ __device__ void block_accumulate(const unsigned long long (&v)[K], unsigned long
     unsigned long long t = 0;
     const int nw = blockDim.x >> 6;
     for (int i = 0; i < nw; ++i) t += part[threadIdx.x][i];
-    if (t) atomicAdd(dst[threadIdx.x], t);
+    G.partials[(size_t)blockIdx.x * kPartials + threadIdx.x] = t;
   }
 }
 
@@ -94,37 +94,132 @@ __device__ __forceinline__ int bucket_of(const DevG<RowT> &G, int64_t deg) {
   return deg <= G.t1 ? kSmall : (deg <= G.t2 ? kMedium : kLarge);
 }
 
-// Appends the lanes' discovered vertices to queue set `qn`, split by degree
+// Workgroup staging of discovered vertices in LDS, one buffer per degree
+// class.  Lanes reserve slots with LDS atomics; the workgroup copies the
+// buffers out with one global atomicAdd per class at the end.  Slots past a
+// buffer's capacity go straight to the global queue.  Layout of the dynamic
+// LDS: counts[4] | small[4 * bs] | medium[bs] | large[bs / 2] (8-byte entries).
+struct Stage {
+  unsigned *cnt;
+  int32_t *small;
+  int32_t *medium;
+  uint64_t *large;
+  unsigned cap_small, cap_medium, cap_large;
+  __device__ unsigned cap(int b) const {
+    return b == kSmall ? cap_small : (b == kMedium ? cap_medium : cap_large);
+  }
+};
+
+__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)24 * bs; }
+
+__device__ __forceinline__ Stage stage_open(char *lds) {
+  const unsigned bs = blockDim.x;
+  Stage S;
+  S.cnt = reinterpret_cast<unsigned *>(lds);
+  S.small = reinterpret_cast<int32_t *>(lds + 16);
+  S.medium = S.small + 4 * bs;
+  S.large = reinterpret_cast<uint64_t *>(S.medium + bs);
+  S.cap_small = 4 * bs;
+  S.cap_medium = bs;
+  S.cap_large = bs / 2;
+  if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  return S;
+}
+
+template <class RowT>
+__device__ __forceinline__ int32_t *global_queue(const DevG<RowT> &G, int qn, int b) {
+  return b == kSmall ? (qn ? G.qs[1] : G.qs[0]) : (qn ? G.qm[1] : G.qm[0]);
+}
+
+// Appends the lanes' discovered vertices (queue set `qn`), split by degree
 // class.  Must be called by all lanes of a wavefront together.
 template <class RowT>
-__device__ __forceinline__ void wave_append(const DevG<RowT> &G, int qn, bool found, int32_t v, int64_t deg) {
+__device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, int qn, bool found,
+                                           int32_t v, int64_t deg) {
   const int b = found ? bucket_of(G, deg) : -1;
-  Ctl *c = G.ctl;
+  const int lane = lane_id();
 #pragma unroll
   for (int bb = kSmall; bb <= kMedium; ++bb) {
     const uint64_t m = __ballot(b == bb);
-    if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      unsigned base = 0;
-      if (lane_id() == leader) base = atomicAdd(&c->qcnt[qn][bb], (unsigned)__popcll(m));
-      base = __shfl(base, leader);
-      if (b == bb) {
-        int32_t *q = (bb == kSmall) ? (qn ? G.qs[1] : G.qs[0]) : (qn ? G.qm[1] : G.qm[0]);
-        q[base + lanes_below(m)] = v;
-      }
+    if (!m) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const unsigned k = (unsigned)__popcll(m);
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&S.cnt[bb], k);
+    base = __shfl(base, leader);
+    const unsigned cap = S.cap(bb);
+    const unsigned first_over = base > cap ? base : cap;
+    const unsigned over = base + k > cap ? base + k - first_over : 0;
+    unsigned gbase = 0;
+    if (over) {
+      if (lane == leader) gbase = atomicAdd(&G.ctl->qcnt[qn][bb], over);
+      gbase = __shfl(gbase, leader);
+    }
+    if (b == bb) {
+      const unsigned slot = base + lanes_below(m);
+      if (slot < cap)
+        (bb == kSmall ? S.small : S.medium)[slot] = v;
+      else
+        global_queue(G, qn, bb)[gbase + (slot - first_over)] = v;
     }
   }
   if (b == kLarge) {  // rare: one entry per t2-edge chunk
     const unsigned nch = (unsigned)((deg + G.t2 - 1) / G.t2);
-    const unsigned base = atomicAdd(&c->qcnt[qn][kLarge], nch);
-    uint64_t *q = qn ? G.ql[1] : G.ql[0];
-    for (unsigned k = 0; k < nch; ++k) q[base + k] = ((uint64_t)k << 32) | (uint32_t)v;
+    const unsigned base = atomicAdd(&S.cnt[kLarge], nch);
+    const unsigned cap = S.cap_large;
+    const unsigned first_over = base > cap ? base : cap;
+    const unsigned over = base + nch > cap ? base + nch - first_over : 0;
+    const unsigned gbase = over ? atomicAdd(&G.ctl->qcnt[qn][kLarge], over) : 0;
+    uint64_t *gq = qn ? G.ql[1] : G.ql[0];
+    for (unsigned k = 0; k < nch; ++k) {
+      const unsigned slot = base + k;
+      const uint64_t e = ((uint64_t)k << 32) | (uint32_t)v;
+      if (slot < cap)
+        S.large[slot] = e;
+      else
+        gq[gbase + (slot - first_over)] = e;
+    }
   }
+}
+
+// Copies the staged entries to queue set `qn`.  All threads call it.
+template <class RowT>
+__device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S, int qn) {
+  __shared__ unsigned gbase[3], count[3];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const unsigned b = threadIdx.x;
+    const unsigned bs = blockDim.x;
+    const unsigned cap = b == kSmall ? 4 * bs : (b == kMedium ? bs : bs / 2);  // as in stage_open
+    const unsigned n = S.cnt[b] < cap ? S.cnt[b] : cap;
+    count[b] = n;
+    gbase[b] = n ? atomicAdd(&G.ctl->qcnt[qn][b], n) : 0;
+  }
+  __syncthreads();
+  int32_t *qs = global_queue(G, qn, kSmall);
+  int32_t *qm = global_queue(G, qn, kMedium);
+  uint64_t *ql = qn ? G.ql[1] : G.ql[0];
+  for (unsigned i = threadIdx.x; i < count[kSmall]; i += blockDim.x) qs[gbase[kSmall] + i] = S.small[i];
+  for (unsigned i = threadIdx.x; i < count[kMedium]; i += blockDim.x) qm[gbase[kMedium] + i] = S.medium[i];
+  for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x) ql[gbase[kLarge] + i] = S.large[i];
+}
+
+// Workgroup order that gives each XCD a contiguous range of workgroups
+// (consecutive workgroup ids are dealt round-robin to the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+  constexpr int kXcd = 8;
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblocks / kXcd;
+  if (per == 0 || b >= per * kXcd) return b;
+  return (b % kXcd) * per + b / kXcd;
 }
 
 // ---------------------------------------------------------------------------
 // Initialisation: dist = -1, parent = -1, visited = isolated-vertex mask,
-// then the source at level 0 in queue set 0 (the first level is top-down).
+// both frontier bitmaps and the partial counts cleared, then the source at
+// level 0 in queue set 0
+// (the first level is top-down).
 
 template <class RowT>
 __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
@@ -137,7 +232,12 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
   }
   const int64_t sw = s >> 6;
   const uint64_t sb = 1ull << (s & 63);
-  for (int64_t w = tid; w < G.words; w += stride) G.vis[w] = G.iso[w] | (w == sw ? sb : 0ull);
+  for (int64_t w = tid; w < G.words; w += stride) {
+    G.vis[w] = G.iso[w] | (w == sw ? sb : 0ull);
+    G.bm[0][w] = 0;
+    G.bm[1][w] = 0;
+  }
+  for (int64_t i = tid; i < (int64_t)kMaxBlocks * kPartials; i += stride) G.partials[i] = 0;
   if (tid == 0) {
     Ctl *c = G.ctl;
     const int64_t deg = (int64_t)G.rp[s + 1] - (int64_t)G.rp[s];
@@ -169,17 +269,16 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
       (b == kSmall ? G.qs[0] : G.qm[0])[0] = s;
       c->qcnt[0][b] = 1;
     }
-    c->acc_found = c->acc_found_deg = c->acc_scanned = c->acc_examined = 0;
     c->dist = dist;
     c->parent = parent;
   }
 }
 
-// Discovery step shared by the top-down kernels: lane examines edge target
-// v of frontier vertex u (when `has`), then the wavefront appends.
+// Discovery step shared by the top-down roles: the lane examines edge
+// target v of frontier vertex u (when `has`), then the wavefront stages.
 template <class RowT>
-__device__ __forceinline__ void td_visit(const DevG<RowT> &G, int qn, int32_t level, int32_t *dist,
-                                         int32_t *parent, bool has, int32_t u, int32_t v,
+__device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
+                                         int32_t *dist, int32_t *parent, bool has, int32_t u, int32_t v,
                                          unsigned long long &nfound, unsigned long long &dfound) {
   bool win = false;
   int64_t deg = 0;
@@ -191,99 +290,93 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, int qn, int32_t le
     nfound += 1;
     dfound += (unsigned long long)deg;
   }
-  wave_append(G, qn, win, v, deg);
+  wave_stage(G, S, qn, win, v, deg);
 }
 
-// Top-down, thread per frontier vertex (degree <= t1).  The lanes of a
-// wavefront step through their rows in lock-step so that the append stays
-// wave-converged.
+// Top-down level.  Workgroups take one of three roles by id:
+//   [0, nb_small)                 thread per vertex of degree <= t1; the
+//                                 lanes of a wavefront step through their
+//                                 rows in lock-step;
+//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
+//                                 reading the row 64 neighbours at a time;
+//   the rest                      workgroup per t2-edge chunk of a larger
+//                                 vertex.
 template <class RowT>
-__global__ void k_td_small(DevG<RowT> G) {
+__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med) {
   const Ctl *c = G.ctl;
   if (c->done || c->dir != kTD) return;
+  extern __shared__ __align__(16) char lds[];
+  const Stage S = stage_open(lds);
   const int qc = c->qcur, qn = qc ^ 1;
   const int32_t level = c->level;
   int32_t *dist = c->dist;
   int32_t *parent = c->parent;
-  const int64_t cnt = c->qcnt[qc][kSmall];
-  const int32_t *q = qc ? G.qs[1] : G.qs[0];
+  const int lane = lane_id();
+  const int wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
   unsigned long long nfound = 0, dfound = 0;
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < cnt; base += step) {
-    const int64_t i = base + lane_id();
-    const bool act = i < cnt;
-    const int32_t u = act ? q[i] : 0;
-    const int64_t beg = act ? (int64_t)G.rp[u] : 0;
-    const int64_t end = act ? (int64_t)G.rp[u + 1] : 0;
-    for (int64_t j = beg; __ballot(j < end); ++j) {
-      const bool has = j < end;
-      const int32_t v = has ? G.col[j] : 0;
-      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
+  const int blk = blockIdx.x;
+  if (blk < nb_small) {
+    const int64_t cnt = c->qcnt[qc][kSmall];
+    const int32_t *q = qc ? G.qs[1] : G.qs[0];
+    const int64_t step = (int64_t)nb_small * blockDim.x;
+    for (int64_t base = (int64_t)blk * blockDim.x + wib * kWave; base < cnt; base += step) {
+      const int64_t i = base + lane;
+      const bool act = i < cnt;
+      const int32_t u = act ? q[i] : 0;
+      const int64_t beg = act ? (int64_t)G.rp[u] : 0;
+      const int64_t end = act ? (int64_t)G.rp[u + 1] : 0;
+      for (int64_t j = beg; __ballot(j < end); ++j) {
+        const bool has = j < end;
+        const int32_t v = has ? G.col[j] : 0;
+        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+      }
+    }
+  } else if (blk < nb_small + nb_med) {
+    const int64_t cnt = c->qcnt[qc][kMedium];
+    const int32_t *q = qc ? G.qm[1] : G.qm[0];
+    const int64_t waves = (int64_t)nb_med * wpb;
+    for (int64_t i = (int64_t)(blk - nb_small) * wpb + wib; i < cnt; i += waves) {
+      const int32_t u = q[i];
+      const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
+      for (int64_t b = beg; b < end; b += kWave) {
+        const int64_t j = b + lane;
+        const bool has = j < end;
+        const int32_t v = has ? G.col[j] : 0;
+        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+      }
+    }
+  } else {
+    const int64_t cnt = c->qcnt[qc][kLarge];
+    const uint64_t *q = qc ? G.ql[1] : G.ql[0];
+    const int64_t nbl = (int64_t)gridDim.x - nb_small - nb_med;
+    for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
+      const uint64_t e = q[i];
+      const int32_t u = (int32_t)(uint32_t)e;
+      const int64_t chunk = (int64_t)(e >> 32);
+      const int64_t row_end = (int64_t)G.rp[u + 1];
+      const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
+      const int64_t end = min(row_end, beg + (int64_t)G.t2);
+      for (int64_t b = beg + wib * kWave; b < end; b += blockDim.x) {
+        const int64_t j = b + lane;
+        const bool has = j < end;
+        const int32_t v = has ? G.col[j] : 0;
+        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+      }
     }
   }
-  Ctl *cw = G.ctl;
-  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
+  stage_flush(G, S, qn);
+  block_partials<2>(G, {nfound, dfound});
 }
 
-// Top-down, wavefront per frontier vertex (degree in (t1, t2]): the wave
-// reads the row 64 neighbours at a time (coalesced).
-template <class RowT>
-__global__ void k_td_medium(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kTD) return;
-  const int qc = c->qcur, qn = qc ^ 1;
-  const int32_t level = c->level;
-  int32_t *dist = c->dist;
-  int32_t *parent = c->parent;
-  const int64_t cnt = c->qcnt[qc][kMedium];
-  const int32_t *q = qc ? G.qm[1] : G.qm[0];
-  unsigned long long nfound = 0, dfound = 0;
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < cnt; i += waves) {
-    const int32_t u = q[i];
-    const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
-    for (int64_t b = beg; b < end; b += kWave) {
-      const int64_t j = b + lane_id();
-      const bool has = j < end;
-      const int32_t v = has ? G.col[j] : 0;
-      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
-    }
-  }
-  Ctl *cw = G.ctl;
-  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
-}
+// Bottom-up level: a wavefront owns 64-bit visited words (64 consecutive
+// vertices each), taking a contiguous run of words.  A lane scans its own
+// row kBuUnroll neighbours per step: the neighbour ids and then their
+// frontier words are loaded as independent requests, so a row costs two
+// memory round trips per kBuUnroll neighbours.  Rows longer than tbu are
+// scanned by the whole wavefront 64 neighbours at a time with a ballot early
+// exit.  `examined` counts neighbours up to and including the first hit.
+constexpr int kBuUnroll = 8;
 
-// Top-down, workgroup per t2-edge chunk of a large frontier vertex.
-template <class RowT>
-__global__ void k_td_large(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kTD) return;
-  const int qc = c->qcur, qn = qc ^ 1;
-  const int32_t level = c->level;
-  int32_t *dist = c->dist;
-  int32_t *parent = c->parent;
-  const int64_t cnt = c->qcnt[qc][kLarge];
-  const uint64_t *q = qc ? G.ql[1] : G.ql[0];
-  unsigned long long nfound = 0, dfound = 0;
-  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const uint64_t e = q[i];
-    const int32_t u = (int32_t)(uint32_t)e;
-    const int64_t chunk = (int64_t)(e >> 32);
-    const int64_t row_end = (int64_t)G.rp[u + 1];
-    const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
-    const int64_t end = min(row_end, beg + (int64_t)G.t2);
-    for (int64_t b = beg + (threadIdx.x & ~63); b < end; b += blockDim.x) {
-      const int64_t j = b + lane_id();
-      const bool has = j < end;
-      const int32_t v = has ? G.col[j] : 0;
-      td_visit(G, qn, level, dist, parent, has, u, v, nfound, dfound);
-    }
-  }
-  Ctl *cw = G.ctl;
-  block_accumulate<2>({nfound, dfound}, {&cw->acc_found, &cw->acc_found_deg});
-}
-
-// Bottom-up: a wavefront owns 64-bit visited word w (vertices 64w..64w+63).
 template <class RowT>
 __global__ void k_bu(DevG<RowT> G) {
   const Ctl *c = G.ctl;
@@ -295,8 +388,12 @@ __global__ void k_bu(DevG<RowT> G) {
   int32_t *parent = c->parent;
   const int lane = lane_id();
   unsigned long long nfound = 0, dfound = 0, nscan = 0, nexam = 0;
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < G.words; w += waves) {
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
+  const int64_t per = (G.words + nw - 1) / nw;
+  const int64_t w1 = min(G.words, (gw + 1) * per);
+  for (int64_t w = gw * per; w < w1; ++w) {
     const uint64_t vw = G.vis[w];
     if (vw == ~0ull) {
       if (lane == 0) next[w] = 0;
@@ -313,18 +410,28 @@ __global__ void k_bu(DevG<RowT> G) {
       heavy = (end - beg) > G.tbu;
       if (!heavy) {
         ex = end - beg;
-        for (int64_t j = beg; j < end; ++j) {
-          const int32_t x = G.col[j];
-          if ((front[x >> 6] >> (x & 63)) & 1ull) {
+        for (int64_t j0 = beg; j0 < end; j0 += kBuUnroll) {
+          int32_t x[kBuUnroll];
+          uint64_t f[kBuUnroll];
+#pragma unroll
+          for (int k = 0; k < kBuUnroll; ++k) x[k] = (j0 + k < end) ? G.col[j0 + k] : -1;
+#pragma unroll
+          for (int k = 0; k < kBuUnroll; ++k) f[k] = (x[k] >= 0) ? front[x[k] >> 6] : 0ull;
+          int first = -1;
+#pragma unroll
+          for (int k = kBuUnroll - 1; k >= 0; --k)
+            if (x[k] >= 0 && ((f[k] >> (x[k] & 63)) & 1ull)) first = k;
+          if (first >= 0) {
             found = true;
-            hit = x;
-            ex = j - beg + 1;
+#pragma unroll
+            for (int k = 0; k < kBuUnroll; ++k)
+              if (k == first) hit = x[k];
+            ex = j0 - beg + first + 1;
             break;
           }
         }
       }
     }
-    // Long rows: the whole wavefront scans one row at a time.
     uint64_t hm = __ballot(heavy);
     while (hm) {
       const int l = __ffsll((unsigned long long)hm) - 1;
@@ -370,18 +477,36 @@ __global__ void k_bu(DevG<RowT> G) {
     nscan += unvisited ? 1 : 0;
     nexam += (unsigned long long)ex;
   }
-  Ctl *cw = G.ctl;
-  block_accumulate<4>({nfound, dfound, nscan, nexam},
-                      {&cw->acc_found, &cw->acc_found_deg, &cw->acc_scanned, &cw->acc_examined});
+  block_partials<4>(G, {nfound, dfound, nscan, nexam});
 }
 
-// Level bookkeeping and the direction rule (one thread).
-__global__ void k_decide(Ctl *c, LevelRec *recs) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || c->done) return;
+// Level bookkeeping and the direction rule.  The workgroup first reduces and
+// clears the partial counts of the level's kernels; thread 0 then applies
+// the rule.
+__global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigned long long *partials) {
+  __shared__ unsigned long long red[kPartials][16];
+  unsigned long long v[kPartials] = {0, 0, 0, 0};
+  for (int i = threadIdx.x; i < kMaxBlocks; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) {
+      v[k] += partials[(size_t)i * kPartials + k];
+      partials[(size_t)i * kPartials + k] = 0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPartials; ++k) {
+    const unsigned long long s = wave_sum(v[k]);
+    if (lane_id() == 0) red[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0 || c->done) return;
+  unsigned long long tot[kPartials] = {0, 0, 0, 0};
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+    for (int k = 0; k < kPartials; ++k) tot[k] += red[k][w];
   const int32_t L = c->level;
   const int32_t cur = c->dir;
-  const int64_t found = (int64_t)c->acc_found;
-  const int64_t fdeg = (int64_t)c->acc_found_deg;
+  const int64_t found = (int64_t)tot[0];
+  const int64_t fdeg = (int64_t)tot[1];
   if (L < c->rec_cap) {
     LevelRec r;
     r.level = L;
@@ -390,8 +515,8 @@ __global__ void k_decide(Ctl *c, LevelRec *recs) {
     r.m_f = c->m_f;
     r.m_u = c->m_u;
     r.found = found;
-    r.scanned = (int64_t)c->acc_scanned;
-    r.examined = (int64_t)c->acc_examined;
+    r.scanned = (int64_t)tot[2];
+    r.examined = (int64_t)tot[3];
     recs[L] = r;
   }
   c->levels_done = L + 1;
@@ -405,7 +530,6 @@ __global__ void k_decide(Ctl *c, LevelRec *recs) {
   } else {
     c->bcur ^= 1;
   }
-  c->acc_found = c->acc_found_deg = c->acc_scanned = c->acc_examined = 0;
   if (found == 0) {
     c->done = 1;
     c->conv = kConvNone;
@@ -432,17 +556,8 @@ __global__ void k_decide(Ctl *c, LevelRec *recs) {
   c->level = L + 1;
 }
 
-// Queue -> bitmap, step 1: clear the target bitmap.
-template <class RowT>
-__global__ void k_conv_clear(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->conv != kConvQ2B) return;
-  uint64_t *bm = c->bcur ? G.bm[1] : G.bm[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < G.words; w += stride) bm[w] = 0;
-}
-
-// Queue -> bitmap, step 2: set the bit of every frontier vertex.
+// Queue -> bitmap: set the bit of every frontier vertex in the current
+// frontier bitmap (kept all-zero while levels run top-down).
 template <class RowT>
 __global__ void k_conv_q2b(DevG<RowT> G) {
   const Ctl *c = G.ctl;
@@ -469,23 +584,33 @@ __global__ void k_conv_q2b(DevG<RowT> G) {
   }
 }
 
-// Bitmap -> queue: compact the frontier bitmap into degree-bucketed queues
-// (ballot + mbcnt per wavefront, one atomic per wavefront and bucket).
+// Bitmap -> queue: compact the frontier bitmap into degree-bucketed queues,
+// clearing each word read (so the bitmap is all-zero again for the next
+// queue -> bitmap conversion).
 template <class RowT>
 __global__ void k_conv_b2q(DevG<RowT> G) {
   const Ctl *c = G.ctl;
   if (c->done || c->conv != kConvB2Q) return;
+  extern __shared__ __align__(16) char lds[];
+  const Stage S = stage_open(lds);
   const int qn = c->qcur;
-  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < G.words; w += waves) {
+  uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
+  const int lane = lane_id();
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
+  const int64_t per = (G.words + nw - 1) / nw;
+  const int64_t w1 = min(G.words, (gw + 1) * per);
+  for (int64_t w = gw * per; w < w1; ++w) {
     const uint64_t word = front[w];
     if (!word) continue;
-    const int64_t v = w * kWave + lane_id();
-    const bool in = (word >> lane_id()) & 1ull;
+    if (lane == 0) front[w] = 0;
+    const int64_t v = w * kWave + lane;
+    const bool in = (word >> lane) & 1ull;
     const int64_t deg = in ? (int64_t)G.rp[v + 1] - (int64_t)G.rp[v] : 0;
-    wave_append(G, qn, in, (int32_t)v, deg);
+    wave_stage(G, S, qn, in, (int32_t)v, deg);
   }
+  stage_flush(G, S, qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,8 +620,6 @@ inline int blocks_for(int64_t items, int64_t per_block, int cap) {
   int64_t b = (items + per_block - 1) / per_block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
-
-constexpr int kMaxBlocks = 1 << 16;
 
 template <class RowT>
 DevG<RowT> make_devg(bfs_graph *g) {
@@ -513,6 +636,7 @@ DevG<RowT> make_devg(bfs_graph *g) {
   }
   G.ctl = g->ctl;
   G.recs = g->recs;
+  G.partials = g->partials;
   G.n = g->n;
   G.words = g->words;
   G.t1 = g->params.td_wave_degree;
@@ -523,45 +647,43 @@ DevG<RowT> make_devg(bfs_graph *g) {
 
 // Launch shapes shared by both loop drivers.
 struct Shapes {
-  int bs;           // threads per workgroup
-  int wpb;          // wavefronts per workgroup
-  int bu_blocks;    // bottom-up grid
-  int words_blocks; // grid for word-parallel conversions
+  int bs;            // threads per workgroup
+  int wpb;           // wavefronts per workgroup
+  int words_blocks;  // grid of the word-parallel kernels (bottom-up, bitmap -> queue)
+  size_t lds;        // dynamic LDS of the staging kernels
 };
 
 Shapes shapes_of(const bfs_graph *g) {
   Shapes s;
   s.bs = g->params.block_size;
   s.wpb = s.bs / kWave;
-  s.bu_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
-  s.words_blocks = blocks_for(g->words, s.bs, kMaxBlocks);
+  s.words_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
+  s.lds = stage_bytes(s.bs);
   return s;
 }
 
-template <class RowT>
-int enqueue_conversions(bfs_graph *g, const DevG<RowT> &G, const Shapes &S, hipStream_t st, int conv,
-                        int64_t qentries_bound) {
-  if (conv == kConvQ2B) {
-    hipLaunchKernelGGL(k_conv_clear<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, st, G);
-    hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(qentries_bound, S.bs, kMaxBlocks)),
-                       dim3(S.bs), 0, st, G);
-  } else if (conv == kConvB2Q) {
-    hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, st, G);
-  }
-  BFS_HIP(hipGetLastError());
-  return BFS_OK;
+// Top-down role sizes: at most 512 + 256 + 256 <= kMaxBlocks workgroups.
+struct TdRoles {
+  int small, med, large;
+};
+
+TdRoles td_roles(const Shapes &S, int64_t c0, int64_t c1, int64_t c2) {
+  TdRoles r;
+  r.small = c0 > 0 ? blocks_for(c0, S.bs, 512) : 0;
+  r.med = c1 > 0 ? blocks_for(c1, S.wpb, 256) : 0;
+  r.large = c2 > 0 ? blocks_for(c2, 1, 256) : 0;
+  if (r.small + r.med + r.large == 0) r.small = 1;
+  return r;
 }
 
 template <class RowT>
-int enqueue_td(const DevG<RowT> &G, const Shapes &S, hipStream_t st, int64_t c0, int64_t c1, int64_t c2) {
-  if (c0 > 0)
-    hipLaunchKernelGGL(k_td_small<RowT>, dim3(blocks_for(c0, S.bs, kMaxBlocks)), dim3(S.bs), 0, st, G);
-  if (c1 > 0)
-    hipLaunchKernelGGL(k_td_medium<RowT>, dim3(blocks_for(c1, S.wpb, kMaxBlocks)), dim3(S.bs), 0, st, G);
-  if (c2 > 0)
-    hipLaunchKernelGGL(k_td_large<RowT>, dim3(blocks_for(c2, 1, kMaxBlocks)), dim3(S.bs), 0, st, G);
-  BFS_HIP(hipGetLastError());
-  return BFS_OK;
+void launch_td(const DevG<RowT> &G, const Shapes &S, const TdRoles &r, hipStream_t st) {
+  hipLaunchKernelGGL(k_td<RowT>, dim3(r.small + r.med + r.large), dim3(S.bs), S.lds, st, G, r.small, r.med);
+}
+
+template <class RowT>
+void launch_level_tail(bfs_graph *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, st, g->ctl, g->recs, g->partials);
 }
 
 int read_ctl(bfs_graph *g, hipStream_t st) {
@@ -579,8 +701,8 @@ hipEvent_t level_event(bfs_graph *g, size_t i) {
   return g->level_events[i];
 }
 
-// Host-driven level loop: after every level the 256-byte control block is
-// read back, so each launch is sized to the frontier it processes.
+// Host-driven level loop: after every level the control block is read back,
+// so each launch is sized to the frontier it processes.
 template <class RowT>
 int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<float> &level_ms) {
   const Shapes S = shapes_of(g);
@@ -591,10 +713,14 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
     if ((rc = read_ctl(g, st))) return rc;
     const Ctl h = *g->ctl_host;
     if (h.done) break;
+    if (h.conv == kConvQ2B) {
+      const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
+      hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(qtotal, S.bs, 4096)), dim3(S.bs), 0, st, G);
+    } else if (h.conv == kConvB2Q) {
+      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, st, G);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
-    if ((rc = enqueue_conversions(g, G, S, st, h.conv, qtotal))) return rc;
-    if (timing) {  // the events bracket the level's direction kernels only
+    if (timing) {  // the events bracket the level's direction kernel only
       e0 = level_event(g, nev++);
       e1 = level_event(g, nev++);
       if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
@@ -606,13 +732,12 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
         c0 = c1 = h.n_f;
         c2 = g->max_degree > G.t2 ? h.m_f / G.t2 + h.n_f : 0;
       }
-      if ((rc = enqueue_td(G, S, st, c0, c1, c2))) return rc;
+      launch_td(G, S, td_roles(S, c0, c1, c2), st);
     } else {
-      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, st, G);
-      BFS_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, st, G);
     }
     if (timing) BFS_HIP(hipEventRecord(e1, st));
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, st, g->ctl, g->recs);
+    launch_level_tail<RowT>(g, st);
     BFS_HIP(hipGetLastError());
   }
   if (timing) {
@@ -627,31 +752,27 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
 }
 
 // Captured level loop: `K` levels of fixed-shape launches whose kernels read
-// the direction / done flags from the control block; replayed until done.
+// the direction / conversion / done flags from the control block; replayed
+// until done.
 template <class RowT>
 int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
   const Shapes S = shapes_of(g);
   hipStream_t cs = g->cap_stream;
   const bool hybrid = policy != BFS_POLICY_TD_ONLY;
-  const bool medium = g->max_degree > G.t1;
-  const bool large = g->max_degree > G.t2;
-  // Fixed grids: enough workgroups to cover the chip several times; the
-  // kernels stride over whatever the control block says.
-  const int td_blocks = blocks_for(g->n, S.bs, 1024);
-  const int med_blocks = blocks_for(g->n, S.wpb, 1024);
+  TdRoles r;
+  r.small = blocks_for(g->n, S.bs, 512);
+  r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, 256) : 0;
+  r.large = g->max_degree > G.t2 ? 256 : 0;
   release_graph_exec(g);
   BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int l = 0; l < K; ++l) {
     if (hybrid) {
-      hipLaunchKernelGGL(k_conv_clear<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, cs, G);
       hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(g->n, S.bs, 4096)), dim3(S.bs), 0, cs, G);
-      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, cs, G);
+      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, cs, G);
     }
-    hipLaunchKernelGGL(k_td_small<RowT>, dim3(td_blocks), dim3(S.bs), 0, cs, G);
-    if (medium) hipLaunchKernelGGL(k_td_medium<RowT>, dim3(med_blocks), dim3(S.bs), 0, cs, G);
-    if (large) hipLaunchKernelGGL(k_td_large<RowT>, dim3(1024), dim3(S.bs), 0, cs, G);
-    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.bu_blocks), dim3(S.bs), 0, cs, G);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, cs, g->ctl, g->recs);
+    launch_td(G, S, r, cs);
+    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, cs, G);
+    launch_level_tail<RowT>(g, cs);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
