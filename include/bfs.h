@@ -93,7 +93,8 @@ typedef struct bfs_params {
   int32_t msbfs_block_size;   /* batched search: threads per workgroup (default 256) */
   int32_t msbfs_bu_percent;   /* batched search: a level runs bottom-up when its frontier
                                  edge count exceeds this percent of nnz (default 5) */
-  int32_t reserved[4];
+  int32_t graph_td_blocks;    /* GRAPH loop: workgroups of the fixed top-down grid (default 128) */
+  int32_t reserved[3];
 } bfs_params;
 
 /* One record per executed level of the last bfs_run on a graph. */

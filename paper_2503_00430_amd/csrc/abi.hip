@@ -96,7 +96,7 @@ static void destroy(bfs_graph *g) {
   DeviceGuard dg(g->device);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   release_graph_exec(g);
-  void *ptrs[] = {g->rp, g->col, g->iso, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
+  void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
                   g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->ctl, g->recs, g->partials,
                   g->ms.seen, g->ms.front, g->ms.next, g->ms.counters};
   for (void *p : ptrs) free_dev(p);
@@ -149,6 +149,7 @@ static bfs_params default_params() {
   p.collect_timing = 0;
   p.msbfs_block_size = 256;
   p.msbfs_bu_percent = 5;
+  p.graph_td_blocks = 128;
   return p;
 }
 
@@ -167,6 +168,8 @@ static int check_params(const bfs_params &p) {
     return fail(BFS_ERR_INVALID_ARG, "unknown loop driver %d", p.loop);
   if (p.graph_chunk_levels < 1 || p.graph_chunk_levels > 4096)
     return fail(BFS_ERR_INVALID_ARG, "graph_chunk_levels must be in [1, 4096]");
+  if (p.graph_td_blocks < 1 || p.graph_td_blocks > 512)
+    return fail(BFS_ERR_INVALID_ARG, "graph_td_blocks must be in [1, 512]");
   if (p.msbfs_bu_percent < 0 || p.msbfs_bu_percent > 100)
     return fail(BFS_ERR_INVALID_ARG, "msbfs_bu_percent must be in [0, 100]");
   return BFS_OK;
@@ -251,6 +254,10 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     g->max_degree = std::max(g->max_degree, d);
   }
   for (int64_t v = n; v < g->words * 64; ++v) iso[v >> 6] |= 1ull << (v & 63);
+  if (g->max_degree > INT32_MAX) {
+    delete g;
+    return fail(BFS_ERR_INVALID_ARG, "a row has more than 2^31 - 1 entries");
+  }
 
   auto bail = [&](int code) {
     destroy(g);
@@ -276,6 +283,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   }
   ALLOC(g->col, nnz);
   ALLOC(g->iso, g->words);
+  ALLOC(g->head, n);
   ALLOC(g->vis, g->words);
   ALLOC(g->bm[0], g->words);
   ALLOC(g->bm[1], g->words);
@@ -314,6 +322,10 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess)
     return bail(fail(BFS_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(e)));
+  {
+    int rc = build_head(g);
+    if (rc) return bail(rc);
+  }
   *out = g;
   return BFS_OK;
 }
@@ -346,7 +358,7 @@ int bfs_set_params(bfs_graph_t g, const bfs_params *p) {
 #define DEF(f) \
   if (q.f == 0) q.f = d.f
   DEF(alpha); DEF(beta); DEF(td_wave_degree); DEF(td_block_degree); DEF(bu_wave_degree);
-  DEF(block_size); DEF(graph_chunk_levels); DEF(msbfs_block_size);
+  DEF(block_size); DEF(graph_chunk_levels); DEF(msbfs_block_size); DEF(graph_td_blocks);
 #undef DEF
   int rc = check_params(q);
   if (rc) return rc;

@@ -50,7 +50,8 @@ struct alignas(256) Ctl {
   int64_t sum_mf;   // sum of m_f over all levels so far (= 2 * TEPS edge count)
   int64_t reached;  // vertices visited so far
   unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
-  unsigned int pad1[2];
+  unsigned int blocks_done;  // workgroups of the running level that have finished
+  unsigned int pad1;
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
 };
@@ -68,6 +69,7 @@ struct DevG {
   const RowT *rp;
   const int32_t *col;
   const uint64_t *iso;  // bit set: vertex has degree 0, or id >= n (tail of last word)
+  const int4 *head;     // per vertex: {degree, first three neighbours or -1}
   uint64_t *vis;        // visited bitmap
   uint64_t *bm[2];      // frontier bitmaps (current / next alternate)
   int32_t *qs[2];       // queue sets: small-degree vertices
@@ -98,6 +100,7 @@ struct bfs_graph {
   void *rp = nullptr;
   int32_t *col = nullptr;
   uint64_t *iso = nullptr;
+  int4 *head = nullptr;  // {degree, first three neighbours or -1} per vertex
   uint64_t *vis = nullptr;
   uint64_t *bm[2] = {nullptr, nullptr};
   int32_t *qs[2] = {nullptr, nullptr};
@@ -150,6 +153,7 @@ struct DeviceGuard {
 };
 
 int resolved_policy(const bfs_graph *g);
+int build_head(bfs_graph *g);  // fills g->head from the resident CSR
 int alloc_single_scratch(bfs_graph *g);  // (re)allocates the large-vertex queues
 void release_graph_exec(bfs_graph *g);
 

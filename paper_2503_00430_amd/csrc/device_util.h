@@ -1,0 +1,39 @@
+// Wavefront helpers shared by the libbfs kernels (wave64, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bfsmi {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of `m` below the calling lane.
+__device__ __forceinline__ unsigned lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+  return x;
+}
+
+// Workgroup order that gives each XCD a contiguous range of workgroups
+// (consecutive workgroup ids are dealt round-robin to the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+  constexpr int kXcd = 8;
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblocks / kXcd;
+  if (per == 0 || b >= per * kXcd) return b;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+}  // namespace bfsmi

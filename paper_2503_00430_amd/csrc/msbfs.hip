@@ -25,25 +25,12 @@
 #include <algorithm>
 
 #include "common.h"
+#include "device_util.h"
 
 namespace cg = cooperative_groups;
 
 namespace bfsmi {
 namespace {
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-__device__ __forceinline__ unsigned long long wave_or(unsigned long long x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
-  return x;
-}
 
 // Device control block of one batched search.
 struct MsCtl {

@@ -43,22 +43,10 @@
 #include <cstring>
 
 #include "common.h"
+#include "device_util.h"
 
 namespace bfsmi {
 namespace {
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-
-// Number of set bits of `m` below the calling lane.
-__device__ __forceinline__ unsigned lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
 
 // Writes the workgroup totals of K per-thread counters to this workgroup's
 // slot of the partials array (plain stores; the decide step reduces them).
@@ -96,9 +84,10 @@ __device__ __forceinline__ int bucket_of(const DevG<RowT> &G, int64_t deg) {
 
 // Workgroup staging of discovered vertices in LDS, one buffer per degree
 // class.  Lanes reserve slots with LDS atomics; the workgroup copies the
-// buffers out with one global atomicAdd per class at the end.  Slots past a
-// buffer's capacity go straight to the global queue.  Layout of the dynamic
-// LDS: counts[4] | small[4 * bs] | medium[bs] | large[bs / 2] (8-byte entries).
+// buffers out with one global atomicAdd per class whenever they are half
+// full (at workgroup-uniform points) and at the end.  Slots past a buffer's
+// capacity go straight to the global queue.  Layout of the dynamic LDS:
+// counts[4] | small[8 * bs] | medium[2 * bs] | large[bs] (8-byte entries).
 struct Stage {
   unsigned *cnt;
   int32_t *small;
@@ -110,18 +99,18 @@ struct Stage {
   }
 };
 
-__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)24 * bs; }
+__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)48 * bs; }
 
 __device__ __forceinline__ Stage stage_open(char *lds) {
   const unsigned bs = blockDim.x;
   Stage S;
   S.cnt = reinterpret_cast<unsigned *>(lds);
   S.small = reinterpret_cast<int32_t *>(lds + 16);
-  S.medium = S.small + 4 * bs;
-  S.large = reinterpret_cast<uint64_t *>(S.medium + bs);
-  S.cap_small = 4 * bs;
-  S.cap_medium = bs;
-  S.cap_large = bs / 2;
+  S.medium = S.small + 8 * bs;
+  S.large = reinterpret_cast<uint64_t *>(S.medium + 2 * bs);
+  S.cap_small = 8 * bs;
+  S.cap_medium = 2 * bs;
+  S.cap_large = bs;
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
   return S;
@@ -183,15 +172,20 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
   }
 }
 
-// Copies the staged entries to queue set `qn`.  All threads call it.
+// Copies the staged entries to queue set `qn` and empties the buffers; with
+// `only_if_half_full`, only when some buffer is at least half full.  All
+// threads of the workgroup call it at the same point.
 template <class RowT>
-__device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S, int qn) {
+__device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S, int qn,
+                                            bool only_if_half_full = false) {
   __shared__ unsigned gbase[3], count[3];
   __syncthreads();
+  const unsigned bs = blockDim.x;
+  if (only_if_half_full && S.cnt[kSmall] < 4 * bs && S.cnt[kMedium] < bs && S.cnt[kLarge] < bs / 2)
+    return;  // uniform: every thread reads the same counts after the barrier
   if (threadIdx.x < 3) {
     const unsigned b = threadIdx.x;
-    const unsigned bs = blockDim.x;
-    const unsigned cap = b == kSmall ? 4 * bs : (b == kMedium ? bs : bs / 2);  // as in stage_open
+    const unsigned cap = b == kSmall ? 8 * bs : (b == kMedium ? 2 * bs : bs);  // as in stage_open
     const unsigned n = S.cnt[b] < cap ? S.cnt[b] : cap;
     count[b] = n;
     gbase[b] = n ? atomicAdd(&G.ctl->qcnt[qn][b], n) : 0;
@@ -203,16 +197,9 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   for (unsigned i = threadIdx.x; i < count[kSmall]; i += blockDim.x) qs[gbase[kSmall] + i] = S.small[i];
   for (unsigned i = threadIdx.x; i < count[kMedium]; i += blockDim.x) qm[gbase[kMedium] + i] = S.medium[i];
   for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x) ql[gbase[kLarge] + i] = S.large[i];
-}
-
-// Workgroup order that gives each XCD a contiguous range of workgroups
-// (consecutive workgroup ids are dealt round-robin to the 8 XCDs).
-__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
-  constexpr int kXcd = 8;
-  const int64_t b = blockIdx.x;
-  const int64_t per = nblocks / kXcd;
-  if (per == 0 || b >= per * kXcd) return b;
-  return (b % kXcd) * per + b / kXcd;
+  __syncthreads();
+  if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -271,238 +258,13 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     }
     c->dist = dist;
     c->parent = parent;
+    c->blocks_done = 0;
   }
 }
 
-// Discovery step shared by the top-down roles: the lane examines edge
-// target v of frontier vertex u (when `has`), then the wavefront stages.
-template <class RowT>
-__device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
-                                         int32_t *dist, int32_t *parent, bool has, int32_t u, int32_t v,
-                                         unsigned long long &nfound, unsigned long long &dfound) {
-  bool win = false;
-  int64_t deg = 0;
-  if (has && claim(G.vis, v)) {
-    win = true;
-    dist[v] = level + 1;  // plain store: the claim made this lane the only writer
-    if (parent) parent[v] = u;
-    deg = (int64_t)G.rp[v + 1] - (int64_t)G.rp[v];
-    nfound += 1;
-    dfound += (unsigned long long)deg;
-  }
-  wave_stage(G, S, qn, win, v, deg);
-}
-
-// Top-down level.  Workgroups take one of three roles by id:
-//   [0, nb_small)                 thread per vertex of degree <= t1; the
-//                                 lanes of a wavefront step through their
-//                                 rows in lock-step;
-//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
-//                                 reading the row 64 neighbours at a time;
-//   the rest                      workgroup per t2-edge chunk of a larger
-//                                 vertex.
-template <class RowT>
-__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kTD) return;
-  extern __shared__ __align__(16) char lds[];
-  const Stage S = stage_open(lds);
-  const int qc = c->qcur, qn = qc ^ 1;
-  const int32_t level = c->level;
-  int32_t *dist = c->dist;
-  int32_t *parent = c->parent;
-  const int lane = lane_id();
-  const int wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
-  unsigned long long nfound = 0, dfound = 0;
-  const int blk = blockIdx.x;
-  if (blk < nb_small) {
-    const int64_t cnt = c->qcnt[qc][kSmall];
-    const int32_t *q = qc ? G.qs[1] : G.qs[0];
-    const int64_t step = (int64_t)nb_small * blockDim.x;
-    for (int64_t base = (int64_t)blk * blockDim.x + wib * kWave; base < cnt; base += step) {
-      const int64_t i = base + lane;
-      const bool act = i < cnt;
-      const int32_t u = act ? q[i] : 0;
-      const int64_t beg = act ? (int64_t)G.rp[u] : 0;
-      const int64_t end = act ? (int64_t)G.rp[u + 1] : 0;
-      for (int64_t j = beg; __ballot(j < end); ++j) {
-        const bool has = j < end;
-        const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
-      }
-    }
-  } else if (blk < nb_small + nb_med) {
-    const int64_t cnt = c->qcnt[qc][kMedium];
-    const int32_t *q = qc ? G.qm[1] : G.qm[0];
-    const int64_t waves = (int64_t)nb_med * wpb;
-    for (int64_t i = (int64_t)(blk - nb_small) * wpb + wib; i < cnt; i += waves) {
-      const int32_t u = q[i];
-      const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
-      for (int64_t b = beg; b < end; b += kWave) {
-        const int64_t j = b + lane;
-        const bool has = j < end;
-        const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
-      }
-    }
-  } else {
-    const int64_t cnt = c->qcnt[qc][kLarge];
-    const uint64_t *q = qc ? G.ql[1] : G.ql[0];
-    const int64_t nbl = (int64_t)gridDim.x - nb_small - nb_med;
-    for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
-      const uint64_t e = q[i];
-      const int32_t u = (int32_t)(uint32_t)e;
-      const int64_t chunk = (int64_t)(e >> 32);
-      const int64_t row_end = (int64_t)G.rp[u + 1];
-      const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
-      const int64_t end = min(row_end, beg + (int64_t)G.t2);
-      for (int64_t b = beg + wib * kWave; b < end; b += blockDim.x) {
-        const int64_t j = b + lane;
-        const bool has = j < end;
-        const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
-      }
-    }
-  }
-  stage_flush(G, S, qn);
-  block_partials<2>(G, {nfound, dfound});
-}
-
-// Bottom-up level: a wavefront owns 64-bit visited words (64 consecutive
-// vertices each), taking a contiguous run of words.  A lane scans its own
-// row kBuUnroll neighbours per step: the neighbour ids and then their
-// frontier words are loaded as independent requests, so a row costs two
-// memory round trips per kBuUnroll neighbours.  Rows longer than tbu are
-// scanned by the whole wavefront 64 neighbours at a time with a ballot early
-// exit.  `examined` counts neighbours up to and including the first hit.
-constexpr int kBuUnroll = 8;
-
-template <class RowT>
-__global__ void k_bu(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kBU) return;
-  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
-  uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
-  const int32_t level = c->level;
-  int32_t *dist = c->dist;
-  int32_t *parent = c->parent;
-  const int lane = lane_id();
-  unsigned long long nfound = 0, dfound = 0, nscan = 0, nexam = 0;
-  const int64_t wpb = blockDim.x >> 6;
-  const int64_t nw = (int64_t)gridDim.x * wpb;
-  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
-  const int64_t per = (G.words + nw - 1) / nw;
-  const int64_t w1 = min(G.words, (gw + 1) * per);
-  for (int64_t w = gw * per; w < w1; ++w) {
-    const uint64_t vw = G.vis[w];
-    if (vw == ~0ull) {
-      if (lane == 0) next[w] = 0;
-      continue;
-    }
-    const int64_t v = w * kWave + lane;  // ids >= n are marked visited in vw
-    const bool unvisited = !((vw >> lane) & 1ull);
-    bool found = false, heavy = false;
-    int32_t hit = -1;
-    int64_t beg = 0, end = 0, ex = 0;
-    if (unvisited) {
-      beg = (int64_t)G.rp[v];
-      end = (int64_t)G.rp[v + 1];
-      heavy = (end - beg) > G.tbu;
-      if (!heavy) {
-        ex = end - beg;
-        for (int64_t j0 = beg; j0 < end; j0 += kBuUnroll) {
-          int32_t x[kBuUnroll];
-          uint64_t f[kBuUnroll];
-#pragma unroll
-          for (int k = 0; k < kBuUnroll; ++k) x[k] = (j0 + k < end) ? G.col[j0 + k] : -1;
-#pragma unroll
-          for (int k = 0; k < kBuUnroll; ++k) f[k] = (x[k] >= 0) ? front[x[k] >> 6] : 0ull;
-          int first = -1;
-#pragma unroll
-          for (int k = kBuUnroll - 1; k >= 0; --k)
-            if (x[k] >= 0 && ((f[k] >> (x[k] & 63)) & 1ull)) first = k;
-          if (first >= 0) {
-            found = true;
-#pragma unroll
-            for (int k = 0; k < kBuUnroll; ++k)
-              if (k == first) hit = x[k];
-            ex = j0 - beg + first + 1;
-            break;
-          }
-        }
-      }
-    }
-    uint64_t hm = __ballot(heavy);
-    while (hm) {
-      const int l = __ffsll((unsigned long long)hm) - 1;
-      hm &= hm - 1;
-      const int64_t b0 = __shfl(beg, l), e0 = __shfl(end, l);
-      int64_t exl = e0 - b0;
-      int32_t hitl = -1;
-      for (int64_t b = b0; b < e0; b += kWave) {
-        const int64_t j = b + lane;
-        int32_t x = 0;
-        bool h = false;
-        if (j < e0) {
-          x = G.col[j];
-          h = (front[x >> 6] >> (x & 63)) & 1ull;
-        }
-        const uint64_t hb = __ballot(h);
-        if (hb) {
-          const int f = __ffsll((unsigned long long)hb) - 1;
-          hitl = __shfl(x, f);
-          exl = b - b0 + f + 1;
-          break;
-        }
-      }
-      if (lane == l) {
-        ex = exl;
-        if (hitl >= 0) {
-          found = true;
-          hit = hitl;
-        }
-      }
-    }
-    const uint64_t fm = __ballot(found);
-    if (lane == 0) {
-      next[w] = fm;
-      if (fm) G.vis[w] = vw | fm;
-    }
-    if (found) {
-      dist[v] = level + 1;
-      if (parent) parent[v] = hit;
-      nfound += 1;
-      dfound += (unsigned long long)(end - beg);
-    }
-    nscan += unvisited ? 1 : 0;
-    nexam += (unsigned long long)ex;
-  }
-  block_partials<4>(G, {nfound, dfound, nscan, nexam});
-}
-
-// Level bookkeeping and the direction rule.  The workgroup first reduces and
-// clears the partial counts of the level's kernels; thread 0 then applies
-// the rule.
-__global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigned long long *partials) {
-  __shared__ unsigned long long red[kPartials][16];
-  unsigned long long v[kPartials] = {0, 0, 0, 0};
-  for (int i = threadIdx.x; i < kMaxBlocks; i += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < kPartials; ++k) {
-      v[k] += partials[(size_t)i * kPartials + k];
-      partials[(size_t)i * kPartials + k] = 0;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kPartials; ++k) {
-    const unsigned long long s = wave_sum(v[k]);
-    if (lane_id() == 0) red[k][threadIdx.x >> 6] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0 || c->done) return;
-  unsigned long long tot[kPartials] = {0, 0, 0, 0};
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
-    for (int k = 0; k < kPartials; ++k) tot[k] += red[k][w];
+// Level bookkeeping and the direction rule, applied by one thread to the
+// level's totals {found, degree sum of found, scanned, examined}.
+__device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&tot)[kPartials]) {
   const int32_t L = c->level;
   const int32_t cur = c->dir;
   const int64_t found = (int64_t)tot[0];
@@ -556,6 +318,297 @@ __global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigne
   c->level = L + 1;
 }
 
+// Reduces (and clears) the partial counts of `nblocks` workgroups; every
+// thread of the calling workgroup takes part, thread 0 receives the totals.
+__device__ void reduce_partials(unsigned long long *partials, int nblocks, unsigned long long (&tot)[kPartials]) {
+  __shared__ unsigned long long red[kPartials][16];
+  unsigned long long v[kPartials] = {0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) {
+      unsigned long long *p = partials + (size_t)i * kPartials + k;
+      v[k] += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPartials; ++k) {
+    const unsigned long long s = wave_sum(v[k]);
+    if (lane_id() == 0) red[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < kPartials; ++k) tot[k] = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+      for (int k = 0; k < kPartials; ++k) tot[k] += red[k][w];
+  }
+}
+
+// Discovery step shared by the top-down roles: the lane examines edge
+// target v of frontier vertex u (when `has`), then the wavefront stages.
+template <class RowT>
+__device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
+                                         int32_t *dist, int32_t *parent, bool has, int32_t u, int32_t v,
+                                         unsigned long long &nfound, unsigned long long &dfound) {
+  bool win = false;
+  int64_t deg = 0;
+  if (has && claim(G.vis, v)) {
+    win = true;
+    dist[v] = level + 1;  // plain store: the claim made this lane the only writer
+    if (parent) parent[v] = u;
+    deg = G.head[v].x;
+    nfound += 1;
+    dfound += (unsigned long long)deg;
+  }
+  wave_stage(G, S, qn, win, v, deg);
+}
+
+// Top-down level.  Workgroups take one of three roles by id:
+//   [0, nb_small)                 thread per vertex of degree <= t1; the
+//                                 lanes of a wavefront step through their
+//                                 rows in lock-step;
+//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
+//                                 reading the row 64 neighbours at a time;
+//   the rest                      workgroup per t2-edge chunk of a larger
+//                                 vertex.
+template <class RowT>
+__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fused_decide) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kTD) return;
+  extern __shared__ __align__(16) char lds[];
+  const Stage S = stage_open(lds);
+  const int qc = c->qcur, qn = qc ^ 1;
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int lane = lane_id();
+  const int wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  unsigned long long nfound = 0, dfound = 0;
+  const int blk = blockIdx.x;
+  // Every role iterates in workgroup-uniform rounds so that the staging
+  // buffers can be flushed between rounds.
+  if (blk < nb_small) {
+    const int64_t cnt = c->qcnt[qc][kSmall];
+    const int32_t *q = qc ? G.qs[1] : G.qs[0];
+    const int64_t step = (int64_t)nb_small * blockDim.x;
+    for (int64_t round = (int64_t)blk * blockDim.x; round < cnt; round += step) {
+      const int64_t i = round + wib * kWave + lane;
+      const bool act = i < cnt;
+      const int32_t u = act ? q[i] : 0;
+      int4 h = make_int4(0, -1, -1, -1);
+      int64_t row0 = 0;
+      if (act) {
+        h = G.head[u];  // degree and first three neighbours
+        row0 = (int64_t)G.rp[u];  // issued together with the head load
+      }
+      const int64_t deg = h.x;
+      for (int64_t j = 0; __ballot(j < deg); ++j) {  // j is uniform across the wavefront
+        const bool has = j < deg;
+        int32_t v = 0;
+        if (has) v = j == 0 ? h.y : j == 1 ? h.z : j == 2 ? h.w : G.col[row0 + j];
+        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+      }
+      stage_flush(G, S, qn, true);
+    }
+  } else if (blk < nb_small + nb_med) {
+    const int64_t cnt = c->qcnt[qc][kMedium];
+    const int32_t *q = qc ? G.qm[1] : G.qm[0];
+    const int64_t waves = (int64_t)nb_med * wpb;
+    for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < cnt; round += waves) {
+      const int64_t i = round + wib;
+      if (i < cnt) {  // uniform within the wavefront
+        const int32_t u = q[i];
+        const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
+        for (int64_t b = beg; b < end; b += kWave) {
+          const int64_t j = b + lane;
+          const bool has = j < end;
+          const int32_t v = has ? G.col[j] : 0;
+          td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+        }
+      }
+      stage_flush(G, S, qn, true);
+    }
+  } else {
+    const int64_t cnt = c->qcnt[qc][kLarge];
+    const uint64_t *q = qc ? G.ql[1] : G.ql[0];
+    const int64_t nbl = (int64_t)gridDim.x - nb_small - nb_med;
+    for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
+      const uint64_t e = q[i];
+      const int32_t u = (int32_t)(uint32_t)e;
+      const int64_t chunk = (int64_t)(e >> 32);
+      const int64_t row_end = (int64_t)G.rp[u + 1];
+      const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
+      const int64_t end = min(row_end, beg + (int64_t)G.t2);
+      for (int64_t b = beg + wib * kWave; b < end; b += blockDim.x) {
+        const int64_t j = b + lane;
+        const bool has = j < end;
+        const int32_t v = has ? G.col[j] : 0;
+        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+      }
+      stage_flush(G, S, qn, true);
+    }
+  }
+  stage_flush(G, S, qn);
+  block_partials<2>(G, {nfound, dfound});
+  if (fused_decide) {
+    // The last workgroup to finish applies the decide step (saves a launch
+    // per level when the grid is small).
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      last = atomicAdd(&G.ctl->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+      __threadfence();
+      unsigned long long tot[kPartials];
+      reduce_partials(G.partials, gridDim.x, tot);
+      if (threadIdx.x == 0) {
+        G.ctl->blocks_done = 0;
+        decide_apply(G.ctl, G.recs, tot);
+      }
+    }
+  }
+}
+
+// Bottom-up level: a wavefront owns 64-bit visited words (64 consecutive
+// vertices each), taking a contiguous run of words.  A lane scans its own
+// row kBuUnroll neighbours per step: the neighbour ids and then their
+// frontier words are loaded as independent requests, so a row costs two
+// memory round trips per kBuUnroll neighbours.  Rows longer than tbu are
+// scanned by the whole wavefront 64 neighbours at a time with a ballot early
+// exit.  `examined` counts neighbours up to and including the first hit.
+constexpr int kBuUnroll = 8;
+
+template <class RowT>
+__global__ void k_bu(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kBU) return;
+  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
+  uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
+  const int32_t level = c->level;
+  int32_t *dist = c->dist;
+  int32_t *parent = c->parent;
+  const int lane = lane_id();
+  unsigned long long nfound = 0, dfound = 0, nscan = 0, nexam = 0;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
+  const int64_t per = (G.words + nw - 1) / nw;
+  const int64_t w1 = min(G.words, (gw + 1) * per);
+  for (int64_t w = gw * per; w < w1; ++w) {
+    const uint64_t vw = G.vis[w];
+    if (vw == ~0ull) {
+      if (lane == 0) next[w] = 0;
+      continue;
+    }
+    const int64_t v = w * kWave + lane;  // ids >= n are marked visited in vw
+    const bool unvisited = !((vw >> lane) & 1ull);
+    bool found = false, heavy = false;
+    int32_t hit = -1;
+    int64_t deg = 0, row0 = 0, ex = 0;
+    if (unvisited) {
+      // first three neighbours from the head record: one coalesced load
+      const int4 h = G.head[v];
+      deg = h.x;
+      ex = deg;
+      const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
+      const uint64_t f0 = x0 >= 0 ? front[x0 >> 6] : 0ull;
+      const uint64_t f1 = x1 >= 0 ? front[x1 >> 6] : 0ull;
+      const uint64_t f2 = x2 >= 0 ? front[x2 >> 6] : 0ull;
+      if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
+        found = true; hit = x0; ex = 1;
+      } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
+        found = true; hit = x1; ex = 2;
+      } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
+        found = true; hit = x2; ex = 3;
+      } else if (deg > 3) {
+        row0 = (int64_t)G.rp[v];
+        heavy = deg > G.tbu;
+        if (!heavy) {
+          const int64_t end = row0 + deg;
+          for (int64_t j0 = row0 + 3; j0 < end; j0 += kBuUnroll) {
+            int32_t x[kBuUnroll];
+            uint64_t f[kBuUnroll];
+#pragma unroll
+            for (int k = 0; k < kBuUnroll; ++k) x[k] = (j0 + k < end) ? G.col[j0 + k] : -1;
+#pragma unroll
+            for (int k = 0; k < kBuUnroll; ++k) f[k] = (x[k] >= 0) ? front[x[k] >> 6] : 0ull;
+            int first = -1;
+#pragma unroll
+            for (int k = kBuUnroll - 1; k >= 0; --k)
+              if (x[k] >= 0 && ((f[k] >> (x[k] & 63)) & 1ull)) first = k;
+            if (first >= 0) {
+              found = true;
+#pragma unroll
+              for (int k = 0; k < kBuUnroll; ++k)
+                if (k == first) hit = x[k];
+              ex = j0 - row0 + first + 1;
+              break;
+            }
+          }
+        }
+      }
+    }
+    // Long rows: the whole wavefront scans the rest of one row at a time.
+    uint64_t hm = __ballot(heavy);
+    while (hm) {
+      const int l = __ffsll((unsigned long long)hm) - 1;
+      hm &= hm - 1;
+      const int64_t r0 = __shfl(row0, l);
+      const int64_t e0 = r0 + __shfl(deg, l);
+      int64_t exl = e0 - r0;
+      int32_t hitl = -1;
+      for (int64_t b = r0 + 3; b < e0; b += kWave) {
+        const int64_t j = b + lane;
+        int32_t x = 0;
+        bool h = false;
+        if (j < e0) {
+          x = G.col[j];
+          h = (front[x >> 6] >> (x & 63)) & 1ull;
+        }
+        const uint64_t hb = __ballot(h);
+        if (hb) {
+          const int f = __ffsll((unsigned long long)hb) - 1;
+          hitl = __shfl(x, f);
+          exl = b - r0 + f + 1;
+          break;
+        }
+      }
+      if (lane == l) {
+        ex = exl;
+        if (hitl >= 0) {
+          found = true;
+          hit = hitl;
+        }
+      }
+    }
+    const uint64_t fm = __ballot(found);
+    if (lane == 0) {
+      next[w] = fm;
+      if (fm) G.vis[w] = vw | fm;
+    }
+    if (found) {
+      dist[v] = level + 1;
+      if (parent) parent[v] = hit;
+      nfound += 1;
+      dfound += (unsigned long long)deg;
+    }
+    nscan += unvisited ? 1 : 0;
+    nexam += (unsigned long long)ex;
+  }
+  block_partials<4>(G, {nfound, dfound, nscan, nexam});
+}
+
+// Separate decide step: one workgroup after the level's kernels.
+__global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigned long long *partials) {
+  unsigned long long tot[kPartials];
+  reduce_partials(partials, kMaxBlocks, tot);
+  if (threadIdx.x != 0 || c->done) return;
+  decide_apply(c, recs, tot);
+}
+
 // Queue -> bitmap: set the bit of every frontier vertex in the current
 // frontier bitmap (kept all-zero while levels run top-down).
 template <class RowT>
@@ -601,16 +654,32 @@ __global__ void k_conv_b2q(DevG<RowT> G) {
   const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
   const int64_t per = (G.words + nw - 1) / nw;
   const int64_t w1 = min(G.words, (gw + 1) * per);
-  for (int64_t w = gw * per; w < w1; ++w) {
-    const uint64_t word = front[w];
-    if (!word) continue;
-    if (lane == 0) front[w] = 0;
-    const int64_t v = w * kWave + lane;
-    const bool in = (word >> lane) & 1ull;
-    const int64_t deg = in ? (int64_t)G.rp[v + 1] - (int64_t)G.rp[v] : 0;
-    wave_stage(G, S, qn, in, (int32_t)v, deg);
+  for (int64_t k = 0; k < per; ++k) {  // workgroup-uniform rounds
+    const int64_t w = gw * per + k;
+    const uint64_t word = w < w1 ? front[w] : 0ull;
+    if (word) {  // uniform within the wavefront
+      if (lane == 0) front[w] = 0;
+      const int64_t v = w * kWave + lane;
+      const bool in = (word >> lane) & 1ull;
+      const int64_t deg = in ? (int64_t)G.head[v].x : 0;
+      wave_stage(G, S, qn, in, (int32_t)v, deg);
+    }
+    stage_flush(G, S, qn, true);
   }
   stage_flush(G, S, qn);
+}
+
+// Head records: degree and the first three neighbours (-1 where the row is
+// shorter), so short rows and most bottom-up hits need one coalesced 16-byte
+// load instead of a row-offset pair and a neighbour-id line.
+template <class RowT>
+__global__ void k_build_head(const RowT *rp, const int32_t *col, int4 *head, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t b = (int64_t)rp[v], e = (int64_t)rp[v + 1];
+    head[v] = make_int4((int)(e - b), b < e ? col[b] : -1, b + 1 < e ? col[b + 1] : -1,
+                        b + 2 < e ? col[b + 2] : -1);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -627,6 +696,7 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.rp = static_cast<const RowT *>(g->rp);
   G.col = g->col;
   G.iso = g->iso;
+  G.head = g->head;
   G.vis = g->vis;
   for (int s = 0; s < 2; ++s) {
     G.bm[s] = g->bm[s];
@@ -677,8 +747,9 @@ TdRoles td_roles(const Shapes &S, int64_t c0, int64_t c1, int64_t c2) {
 }
 
 template <class RowT>
-void launch_td(const DevG<RowT> &G, const Shapes &S, const TdRoles &r, hipStream_t st) {
-  hipLaunchKernelGGL(k_td<RowT>, dim3(r.small + r.med + r.large), dim3(S.bs), S.lds, st, G, r.small, r.med);
+void launch_td(const DevG<RowT> &G, const Shapes &S, const TdRoles &r, hipStream_t st, int fused_decide = 0) {
+  hipLaunchKernelGGL(k_td<RowT>, dim3(r.small + r.med + r.large), dim3(S.bs), S.lds, st, G, r.small, r.med,
+                     fused_decide);
 }
 
 template <class RowT>
@@ -759,10 +830,13 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
   const Shapes S = shapes_of(g);
   hipStream_t cs = g->cap_stream;
   const bool hybrid = policy != BFS_POLICY_TD_ONLY;
+  // fixed role sizes, scaled by graph_td_blocks
+  const int gb = g->params.graph_td_blocks;
   TdRoles r;
-  r.small = blocks_for(g->n, S.bs, 512);
-  r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, 256) : 0;
-  r.large = g->max_degree > G.t2 ? 256 : 0;
+  r.small = blocks_for(g->n, S.bs, gb);
+  r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, std::max(1, gb / 2)) : 0;
+  r.large = g->max_degree > G.t2 ? std::max(1, gb / 2) : 0;
+  const int fused = hybrid ? 0 : 1;  // top-down only: the last workgroup decides
   release_graph_exec(g);
   BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int l = 0; l < K; ++l) {
@@ -770,9 +844,9 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
       hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(g->n, S.bs, 4096)), dim3(S.bs), 0, cs, G);
       hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, cs, G);
     }
-    launch_td(G, S, r, cs);
+    launch_td(G, S, r, cs, fused);
     if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, cs, G);
-    launch_level_tail<RowT>(g, cs);
+    if (!fused) launch_level_tail<RowT>(g, cs);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
@@ -853,6 +927,20 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
 }
 
 }  // namespace
+
+int build_head(bfs_graph *g) {
+  const int bs = 256;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + bs - 1) / bs, 8192));
+  if (g->rp64)
+    hipLaunchKernelGGL(k_build_head<int64_t>, dim3(blocks), dim3(bs), 0, nullptr,
+                       static_cast<const int64_t *>(g->rp), g->col, g->head, g->n);
+  else
+    hipLaunchKernelGGL(k_build_head<int32_t>, dim3(blocks), dim3(bs), 0, nullptr,
+                       static_cast<const int32_t *>(g->rp), g->col, g->head, g->n);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipDeviceSynchronize());
+  return BFS_OK;
+}
 
 int run_single(bfs_graph *g, int32_t source, int32_t *dist, int32_t *parent) {
   return g->rp64 ? run_impl<int64_t>(g, source, dist, parent) : run_impl<int32_t>(g, source, dist, parent);
