@@ -240,7 +240,10 @@ int bfs_serve_destroy(bfs_server_t s);
  * Queues one request: the single-source search of bfs_run on graph g from
  * `source`.  Never waits for the GPU.  dist_out (device int32[n]) and
  * parent_out (device int32[n] or NULL) have bfs_run's meaning and must stay
- * allocated until the request reports DONE or FAILED.
+ * allocated until the request reports DONE or FAILED.  The server writes
+ * them from its own streams, which are not ordered with the caller's: work
+ * that still writes these buffers must have completed before the call, and
+ * they hold the result once the request reports DONE.
  * Errors: INVALID_ARG; OUT_OF_MEMORY when the request alone exceeds the
  * budget.
  */

@@ -73,6 +73,7 @@ def submit(bfs, srv, gs, handles, name, s, want_parent):
     n = gs[name].n
     d = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     p = torch.full((n,), -7, dtype=torch.int32, device="cuda") if want_parent else None
+    torch.cuda.synchronize()  # the server writes from its own streams
     t = bfs.bfs_serve_submit(srv, handles[name], s, d, p)
     return t, d, p
 
@@ -168,6 +169,7 @@ def test_destroy_graph_busy(bfs):
     gh = upload(g)
     srv = bfs.bfs_serve_create(1 << 32, 4)
     d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
     t = bfs.bfs_serve_submit(srv, gh, 0, d)
     try:
         gh.close()
