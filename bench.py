@@ -153,6 +153,122 @@ def bench_mesh(bfs, torch, reps=2):
             "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2)}
 
 
+# Serving pool: RMAT scales 14-22 and 23, perturbed lattices without
+# shortcuts, and uniform random graphs of 2^20 vertices; graphs are drawn
+# Zipf(1.1) in this order, sources uniformly among non-isolated vertices.
+SERVE_POOL = [("rmat", 14), ("rmat", 16), ("rmat", 18), ("rmat", 20), ("rmat", 22),
+              ("grid", 512), ("grid", 1024), ("grid", 2048),
+              ("urand", 8), ("urand", 16), ("urand", 32), ("rmat", 23)]
+
+
+def _serve_graph(kind, size):
+    import graphgen
+    if kind == "rmat":
+        return graphgen.rmat(size)
+    if kind == "grid":
+        return graphgen.grid(size, p_shortcut=0.0)
+    return graphgen.urand(1 << 20, size)
+
+
+def _component_edges(g):
+    """Undirected edges of each vertex's component (TEPS numerator per source)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    a = csr_matrix((np.ones(g.nnz, np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    _, lab = connected_components(a, directed=False)
+    per = np.bincount(lab, weights=np.diff(g.row_ptr), minlength=lab.max() + 1) / 2
+    return per[lab]
+
+
+def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=6000):
+    """Poisson arrivals over the 12-graph pool through the server, against
+    the same trace served first-come-first-served by plain bfs_run."""
+    graphs, handles, edges, nz = [], [], [], []
+    for kind, size in SERVE_POOL:
+        g = _serve_graph(kind, size)
+        graphs.append(g)
+        handles.append(bfs.bfs_create_graph(g.row_ptr, g.col_idx))
+        edges.append(_component_edges(g))
+        nz.append(np.flatnonzero(g.degree > 0))
+    rng = np.random.default_rng(seed)
+    zipf = 1.0 / np.arange(1, len(graphs) + 1) ** 1.1
+    zipf /= zipf.sum()
+    gid = rng.choice(len(graphs), size=requests, p=zipf)
+    src = [int(nz[k][rng.integers(len(nz[k]))]) for k in gid]
+    m_s = np.array([edges[k][s] for k, s in zip(gid, src)])
+    # output buffers: a pool per graph, reused once a request is done
+    pool_size = 128
+    bufs = [[torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(pool_size)] for g in graphs]
+    torch.cuda.synchronize()
+
+    # plain first-come-first-served: each request's own run time, queued in order
+    dist = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
+    for k in range(len(graphs)):
+        bfs.bfs_run(handles[k], int(nz[k][0]), dist[k])
+    run_s = np.empty(requests)
+    for i, (k, s) in enumerate(zip(gid, src)):
+        bfs.bfs_run(handles[k], s, dist[k])
+        run_s[i] = bfs.bfs_get_run_stats(handles[k])[0]["host_ms"] / 1e3
+    plain_rate = requests / run_s.sum()
+
+    def serve(arrivals):
+        srv = bfs.bfs_serve_create(8 << 30, 64)
+        free = [list(range(pool_size)) for _ in graphs]
+        inflight = {}
+        lat = np.zeros(requests)
+        i = 0
+        t0_ns = time.perf_counter_ns()  # CLOCK_MONOTONIC, as the server's timestamps
+        t0 = t0_ns / 1e9
+        while i < requests or inflight:
+            now = time.perf_counter() - t0
+            while i < requests and arrivals[i] <= now and free[gid[i]]:
+                b = free[gid[i]].pop()
+                t = bfs.bfs_serve_submit(srv, handles[gid[i]], src[i], bufs[gid[i]][b])
+                inflight[t] = (i, b)
+                i += 1
+            for t in list(inflight):
+                state, st = bfs.bfs_serve_poll(srv, t)
+                if state == bfs.BFS_REQ_DONE:
+                    j, b = inflight.pop(t)
+                    # latency from the request's arrival time in the trace
+                    lat[j] = (st["t_done_ns"] - t0_ns) / 1e9 - arrivals[j]
+                    free[gid[j]].append(b)
+                elif state == bfs.BFS_REQ_FAILED:
+                    raise RuntimeError("a served request failed")
+            if i < requests and not inflight and arrivals[i] > now:
+                time.sleep(min(arrivals[i] - now, 0.001))
+        wall = time.perf_counter() - t0
+        bfs.bfs_serve_destroy(srv)
+        return lat, wall
+
+    # saturation: every request submitted at once
+    lat0, wall0 = serve(np.zeros(requests))
+    sat = requests / wall0
+    out = {"pool": [f"{k}{z}" for k, z in SERVE_POOL], "requests_per_rate": requests,
+           "saturation_rps": round(sat, 1), "plain_fcfs_capacity_rps": round(plain_rate, 1),
+           "saturation_gteps": round(m_s.sum() / wall0 / 1e9, 3), "rates": []}
+    for frac in rates:
+        rate = frac * sat
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=requests))
+        lat, wall = serve(arrivals)
+        # plain FCFS on the same trace (one request at a time, in arrival order)
+        finish, fl = 0.0, np.empty(requests)
+        for j in range(requests):
+            finish = max(finish, arrivals[j]) + run_s[j]
+            fl[j] = finish - arrivals[j]
+        out["rates"].append({
+            "rate_rps": round(rate, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "gteps": round(m_s.sum() / wall / 1e9, 3),
+            "plain_fcfs_p50_ms": round(float(np.percentile(fl, 50)) * 1e3, 3),
+            "plain_fcfs_p99_ms": round(float(np.percentile(fl, 99)) * 1e3, 3),
+            "plain_fcfs_gteps": round(m_s.sum() / max(finish, arrivals[-1]) / 1e9, 3)})
+    for h in handles:
+        h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +276,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and mesh sections")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, mesh and serving sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -275,6 +392,9 @@ def main():
         torch.cuda.empty_cache()
         log("mesh section (grid4096)")
         out["mesh"] = bench_mesh(bfs, torch)
+        torch.cuda.empty_cache()
+        log("serving section (12-graph pool)")
+        out["serving"] = bench_serving(bfs, torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -472,19 +472,127 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
   }
 }
 
-// Bottom-up level: a wavefront owns 64-bit visited words (64 consecutive
-// vertices each), taking a contiguous run of words.  A lane scans its own
-// row kBuUnroll neighbours per step: the neighbour ids and then their
-// frontier words are loaded as independent requests, so a row costs two
-// memory round trips per kBuUnroll neighbours.  Rows longer than tbu are
-// scanned by the whole wavefront 64 neighbours at a time with a ballot early
-// exit.  `examined` counts neighbours up to and including the first hit.
+// Bottom-up level (Section 2, Listing 2: every unvisited vertex looks for a
+// frontier neighbour and stops at the first).  A wavefront owns a contiguous
+// run of 64-bit visited words (64 vertices each), taken 64 words at a time:
+//   1. the 64 visited words are loaded with one coalesced load (a lane each);
+//   2. word by word, each unvisited lane tests the three neighbours of its
+//      head record against the frontier bitmap; the next word's head records
+//      are prefetched while the current word is resolved;
+//   3. lanes that miss and have longer rows are deferred to a per-wavefront
+//      ring in LDS; whenever 64 have gathered, the wavefront scans those 64
+//      rows one per lane (kBuUnroll neighbours per step as independent
+//      loads), rows longer than tbu by the whole wavefront with a ballot
+//      early exit;
+//   4. the found masks collect in LDS and are written as next-frontier and
+//      visited words with one coalesced store per run.
+// `examined` counts neighbours up to and including the first hit.
 constexpr int kBuUnroll = 8;
+constexpr int kRing = 128;  // deferred rows per wavefront (at most 63 + 64 pending)
+
+struct BuWaveLds {
+  int32_t v[kRing];
+  int32_t deg[kRing];
+  uint8_t word[kRing];
+  uint64_t mask[kWave];
+};
+
+__host__ __device__ constexpr size_t bu_lds_bytes(int bs) { return (size_t)(bs / kWave) * sizeof(BuWaveLds); }
+
+// Scans `cnt` (<= 64) deferred rows starting at ring slot `head`, one per
+// lane; records the finds in the LDS masks.
+template <class RowT>
+__device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsigned head, unsigned cnt,
+                                         const uint64_t *front, int64_t sr, int32_t level, int32_t *dist,
+                                         int32_t *parent, unsigned long long &nfound,
+                                         unsigned long long &dfound, unsigned long long &nexam) {
+  const int lane = lane_id();
+  const bool act = (unsigned)lane < cnt;
+  const unsigned slot = (head + lane) % kRing;
+  int32_t v = 0, deg = 0, k = 0;
+  int64_t row0 = 0;
+  if (act) {
+    v = W.v[slot];
+    deg = W.deg[slot];
+    k = W.word[slot];
+    row0 = (int64_t)G.rp[v];
+  }
+  const bool heavy = act && deg > G.tbu;
+  bool found = false;
+  int32_t hit = -1;
+  int64_t ex = deg;
+  if (act && !heavy) {
+    const int64_t end = row0 + deg;
+    for (int64_t j0 = row0 + 3; j0 < end; j0 += kBuUnroll) {
+      int32_t x[kBuUnroll];
+      uint64_t f[kBuUnroll];
+#pragma unroll
+      for (int q = 0; q < kBuUnroll; ++q) x[q] = (j0 + q < end) ? G.col[j0 + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kBuUnroll; ++q) f[q] = (x[q] >= 0) ? front[x[q] >> 6] : 0ull;
+      int first = -1;
+#pragma unroll
+      for (int q = kBuUnroll - 1; q >= 0; --q)
+        if (x[q] >= 0 && ((f[q] >> (x[q] & 63)) & 1ull)) first = q;
+      if (first >= 0) {
+        found = true;
+#pragma unroll
+        for (int q = 0; q < kBuUnroll; ++q)
+          if (q == first) hit = x[q];
+        ex = j0 - row0 + first + 1;
+        break;
+      }
+    }
+  }
+  uint64_t hm = __ballot(heavy);
+  while (hm) {
+    const int l = __ffsll((unsigned long long)hm) - 1;
+    hm &= hm - 1;
+    const int64_t r0 = __shfl(row0, l);
+    const int64_t e0 = r0 + __shfl(deg, l);
+    int64_t exl = e0 - r0;
+    int32_t hitl = -1;
+    for (int64_t b = r0 + 3; b < e0; b += kWave) {
+      const int64_t j = b + lane;
+      int32_t x = 0;
+      bool h = false;
+      if (j < e0) {
+        x = G.col[j];
+        h = (front[x >> 6] >> (x & 63)) & 1ull;
+      }
+      const uint64_t hb = __ballot(h);
+      if (hb) {
+        const int f = __ffsll((unsigned long long)hb) - 1;
+        hitl = __shfl(x, f);
+        exl = b - r0 + f + 1;
+        break;
+      }
+    }
+    if (lane == l) {
+      ex = exl;
+      if (hitl >= 0) {
+        found = true;
+        hit = hitl;
+      }
+    }
+  }
+  if (act) nexam += (unsigned long long)ex;
+  if (found) {
+    dist[v] = level + 1;
+    if (parent) parent[v] = hit;
+    nfound += 1;
+    dfound += (unsigned long long)deg;
+    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[k]), 1ull << (v & 63));
+  }
+  (void)sr;
+}
 
 template <class RowT>
 __global__ void k_bu(DevG<RowT> G) {
   const Ctl *c = G.ctl;
   if (c->done || c->dir != kBU) return;
+  extern __shared__ __align__(16) char lds[];
+  BuWaveLds &W = reinterpret_cast<BuWaveLds *>(lds)[threadIdx.x >> 6];
   const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
   uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
   const int32_t level = c->level;
@@ -496,107 +604,79 @@ __global__ void k_bu(DevG<RowT> G) {
   const int64_t nw = (int64_t)gridDim.x * wpb;
   const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
   const int64_t per = (G.words + nw - 1) / nw;
-  const int64_t w1 = min(G.words, (gw + 1) * per);
-  for (int64_t w = gw * per; w < w1; ++w) {
-    const uint64_t vw = G.vis[w];
-    if (vw == ~0ull) {
-      if (lane == 0) next[w] = 0;
-      continue;
+  const int64_t w_end = min(G.words, (gw + 1) * per);
+  for (int64_t sr = gw * per; sr < w_end; sr += kWave) {
+    const int nwd = (int)min((int64_t)kWave, w_end - sr);
+    const uint64_t my_vis = lane < nwd ? G.vis[sr + lane] : ~0ull;
+    W.mask[lane] = 0;
+    unsigned rhead = 0, rcount = 0;  // deferred ring (wave-uniform)
+    // head records of the first word with unvisited vertices
+    int4 hn = make_int4(0, -1, -1, -1);
+    {
+      const uint64_t vw0 = __shfl(my_vis, 0);
+      if (vw0 != ~0ull && !((vw0 >> lane) & 1ull)) hn = G.head[sr * kWave + lane];
     }
-    const int64_t v = w * kWave + lane;  // ids >= n are marked visited in vw
-    const bool unvisited = !((vw >> lane) & 1ull);
-    bool found = false, heavy = false;
-    int32_t hit = -1;
-    int64_t deg = 0, row0 = 0, ex = 0;
-    if (unvisited) {
-      // first three neighbours from the head record: one coalesced load
-      const int4 h = G.head[v];
-      deg = h.x;
-      ex = deg;
-      const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
-      const uint64_t f0 = x0 >= 0 ? front[x0 >> 6] : 0ull;
-      const uint64_t f1 = x1 >= 0 ? front[x1 >> 6] : 0ull;
-      const uint64_t f2 = x2 >= 0 ? front[x2 >> 6] : 0ull;
-      if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
-        found = true; hit = x0; ex = 1;
-      } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
-        found = true; hit = x1; ex = 2;
-      } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
-        found = true; hit = x2; ex = 3;
-      } else if (deg > 3) {
-        row0 = (int64_t)G.rp[v];
-        heavy = deg > G.tbu;
-        if (!heavy) {
-          const int64_t end = row0 + deg;
-          for (int64_t j0 = row0 + 3; j0 < end; j0 += kBuUnroll) {
-            int32_t x[kBuUnroll];
-            uint64_t f[kBuUnroll];
-#pragma unroll
-            for (int k = 0; k < kBuUnroll; ++k) x[k] = (j0 + k < end) ? G.col[j0 + k] : -1;
-#pragma unroll
-            for (int k = 0; k < kBuUnroll; ++k) f[k] = (x[k] >= 0) ? front[x[k] >> 6] : 0ull;
-            int first = -1;
-#pragma unroll
-            for (int k = kBuUnroll - 1; k >= 0; --k)
-              if (x[k] >= 0 && ((f[k] >> (x[k] & 63)) & 1ull)) first = k;
-            if (first >= 0) {
-              found = true;
-#pragma unroll
-              for (int k = 0; k < kBuUnroll; ++k)
-                if (k == first) hit = x[k];
-              ex = j0 - row0 + first + 1;
-              break;
-            }
-          }
+    for (int k = 0; k < nwd; ++k) {
+      const uint64_t vw = __shfl(my_vis, k);
+      const int4 h = hn;
+      if (k + 1 < nwd) {  // prefetch the next word's head records
+        const uint64_t vw1 = __shfl(my_vis, k + 1);
+        if (vw1 != ~0ull && !((vw1 >> lane) & 1ull)) hn = G.head[(sr + k + 1) * kWave + lane];
+      }
+      if (vw == ~0ull) continue;
+      const int64_t v = (sr + k) * kWave + lane;  // ids >= n are marked visited in vw
+      const bool unvisited = !((vw >> lane) & 1ull);
+      bool found = false, defer = false;
+      int32_t hit = -1;
+      if (unvisited) {
+        const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
+        const uint64_t f0 = x0 >= 0 ? front[x0 >> 6] : 0ull;
+        const uint64_t f1 = x1 >= 0 ? front[x1 >> 6] : 0ull;
+        const uint64_t f2 = x2 >= 0 ? front[x2 >> 6] : 0ull;
+        int64_t ex = h.x;
+        if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
+          found = true; hit = x0; ex = 1;
+        } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
+          found = true; hit = x1; ex = 2;
+        } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
+          found = true; hit = x2; ex = 3;
+        } else if (h.x > 3) {
+          defer = true;  // counted when its row is scanned
+        }
+        if (!defer) nexam += (unsigned long long)ex;
+        nscan += 1;
+        if (found) {
+          dist[v] = level + 1;
+          if (parent) parent[v] = hit;
+          nfound += 1;
+          dfound += (unsigned long long)h.x;
+        }
+      }
+      const uint64_t fm = __ballot(found);
+      if (lane == 0 && fm) W.mask[k] = fm;
+      const uint64_t dm = __ballot(defer);
+      if (dm) {
+        if (defer) {
+          const unsigned slot = (rhead + rcount + lanes_below(dm)) % kRing;
+          W.v[slot] = (int32_t)v;
+          W.deg[slot] = h.x;
+          W.word[slot] = (uint8_t)k;
+        }
+        rcount += (unsigned)__popcll(dm);
+        if (rcount >= kWave) {
+          bu_drain(G, W, rhead, kWave, front, sr, level, dist, parent, nfound, dfound, nexam);
+          rhead = (rhead + kWave) % kRing;
+          rcount -= kWave;
         }
       }
     }
-    // Long rows: the whole wavefront scans the rest of one row at a time.
-    uint64_t hm = __ballot(heavy);
-    while (hm) {
-      const int l = __ffsll((unsigned long long)hm) - 1;
-      hm &= hm - 1;
-      const int64_t r0 = __shfl(row0, l);
-      const int64_t e0 = r0 + __shfl(deg, l);
-      int64_t exl = e0 - r0;
-      int32_t hitl = -1;
-      for (int64_t b = r0 + 3; b < e0; b += kWave) {
-        const int64_t j = b + lane;
-        int32_t x = 0;
-        bool h = false;
-        if (j < e0) {
-          x = G.col[j];
-          h = (front[x >> 6] >> (x & 63)) & 1ull;
-        }
-        const uint64_t hb = __ballot(h);
-        if (hb) {
-          const int f = __ffsll((unsigned long long)hb) - 1;
-          hitl = __shfl(x, f);
-          exl = b - r0 + f + 1;
-          break;
-        }
-      }
-      if (lane == l) {
-        ex = exl;
-        if (hitl >= 0) {
-          found = true;
-          hit = hitl;
-        }
-      }
+    if (rcount) bu_drain(G, W, rhead, rcount, front, sr, level, dist, parent, nfound, dfound, nexam);
+    // one coalesced store of the run's next-frontier and visited words
+    if (lane < nwd) {
+      const uint64_t m = W.mask[lane];
+      next[sr + lane] = m;
+      if (m) G.vis[sr + lane] = my_vis | m;
     }
-    const uint64_t fm = __ballot(found);
-    if (lane == 0) {
-      next[w] = fm;
-      if (fm) G.vis[w] = vw | fm;
-    }
-    if (found) {
-      dist[v] = level + 1;
-      if (parent) parent[v] = hit;
-      nfound += 1;
-      dfound += (unsigned long long)deg;
-    }
-    nscan += unvisited ? 1 : 0;
-    nexam += (unsigned long long)ex;
   }
   block_partials<4>(G, {nfound, dfound, nscan, nexam});
 }
@@ -805,7 +885,7 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       }
       launch_td(G, S, td_roles(S, c0, c1, c2), st);
     } else {
-      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, st, G);
+      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), bu_lds_bytes(S.bs), st, G);
     }
     if (timing) BFS_HIP(hipEventRecord(e1, st));
     launch_level_tail<RowT>(g, st);
@@ -845,7 +925,7 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
       hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, cs, G);
     }
     launch_td(G, S, r, cs, fused);
-    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), 0, cs, G);
+    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), bu_lds_bytes(S.bs), cs, G);
     if (!fused) launch_level_tail<RowT>(g, cs);
   }
   hipGraph_t graph = nullptr;
