@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (harmonic mean, 64 sources) RMAT-24; batched vs plain; p50/p99 latency"
+CREATE_FLAGS = 0x10  # BFS_SORT_NEIGHBORS: rows ordered hub-first when the graph is created
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -103,7 +104,8 @@ def cpu_baseline(g, sources, budget_s=20.0, max_sources=8):
 def bench_batched(bfs, torch, reps=3):
     """RMAT scale 22, 64 sources: one bfs_run_batch against 64 bfs_run calls."""
     g, sources, _ = make_graph("rmat22")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx)
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS)
+    autotune.apply_tuned(gh)
     out8 = torch.empty((len(sources), g.n), dtype=torch.uint8, device="cuda")
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     bfs.bfs_run_batch(gh, sources, out8)  # warm-up
@@ -133,7 +135,8 @@ def bench_batched(bfs, torch, reps=3):
 def bench_mesh(bfs, torch, reps=2):
     """4096 x 4096 perturbed lattice, 16 sources (top-down only, captured loop)."""
     g, sources, _ = make_graph("grid4096")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx)
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS)
+    autotune.apply_tuned(gh)
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     bfs.bfs_run(gh, int(sources[0]), dist)  # warm-up (captures the level loop)
     per = {}
@@ -187,7 +190,8 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
     for kind, size in SERVE_POOL:
         g = _serve_graph(kind, size)
         graphs.append(g)
-        handles.append(bfs.bfs_create_graph(g.row_ptr, g.col_idx))
+        handles.append(bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS))
+        autotune.apply_tuned(handles[-1])
         edges.append(_component_edges(g))
         nz.append(np.flatnonzero(g.degree > 0))
     rng = np.random.default_rng(seed)
@@ -276,6 +280,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, mesh and serving sections")
     args = ap.parse_args()
@@ -285,18 +291,31 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # A copy of known size: 1 GiB read and 1 GiB written per launch.
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "launches": 5}))
+        return
     import paper_2503_00430_amd as bfs
     if not os.path.exists(bfs.library_path()):
         from paper_2503_00430_amd import build as libbuild
         libbuild.build()
+    global autotune
+    from paper_2503_00430_amd import autotune
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
     t0 = time.time()
     g, sources, rp32 = make_graph(args.workload)
     log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f} s")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, bfs.BFS_ROWPTR32 if rp32 else 0)
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS | (bfs.BFS_ROWPTR32 if rp32 else 0))
     info = bfs.bfs_graph_info_get(gh)
+    tuned = autotune.apply_tuned(gh)
     bfs.bfs_set_params(gh, collect_timing=1)
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -375,8 +394,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}_plain_hybrid_bfs", "n": g.n, "nnz": g.nnz,
                    "sources": len(sources), "row_ptr_bytes": info["row_ptr_bytes"],
-                   "policy": "auto (alpha/beta 14/24 for average degree >= 7, else top-down only)",
-                   "parents": True},
+                   "policy": "auto (alpha/beta for average degree >= 7, else top-down only)",
+                   "neighbour_order": "hub-first (BFS_SORT_NEIGHBORS, at graph creation)",
+                   "params": {k: v for k, v in bfs.bfs_get_params(gh).items()
+                              if k not in ("collect_timing",)},
+                   "tuned_params_applied": bool(tuned), "parents": True},
         "roofline": roofline,
         "gteps_device_time_hm": round(gteps_dev_hm, 3),
         "td_ms_per_bfs": round(td_ms, 4),

@@ -49,6 +49,9 @@ typedef enum bfs_status {
 #define BFS_VALIDATE 0x2u       /* check the CSR structure before accepting it */
 #define BFS_VALIDATE_SYMMETRY 0x4u /* with BFS_VALIDATE: also check v in N(u) <=> u in N(v) */
 #define BFS_ROWPTR32 0x8u       /* keep row offsets as int32 on the device (needs nnz < 2^31) */
+#define BFS_SORT_NEIGHBORS 0x10u /* reorder each row by descending neighbour degree (ties: ascending
+                                    id) in the device copy: bottom-up scans then reach frontier
+                                    vertices sooner; distances are unchanged (needs nnz < 2^31) */
 
 /* Direction policies (bfs_params.policy). */
 typedef enum bfs_policy {
@@ -85,7 +88,7 @@ typedef struct bfs_params {
   int32_t td_block_degree;    /* top-down: degree > this get workgroups, one per
                                  td_block_degree-edge chunk (default 2048) */
   int32_t bu_wave_degree;     /* bottom-up: unvisited vertices with degree > this are
-                                 scanned by the whole wavefront (default 64) */
+                                 scanned by the whole wavefront (default 2048) */
   int32_t block_size;         /* threads per workgroup of the level kernels (default 512) */
   int32_t loop;               /* bfs_loop */
   int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 32) */
@@ -146,7 +149,8 @@ int bfs_default_params(bfs_params *p);
  *   col_idx  nnz int32 neighbour ids in [0, n).  The CSR must be symmetric
  *            (bottom-up levels scan a vertex's own row as its in-edges);
  *            duplicate entries and self-loops are tolerated but count in nnz.
- *   flags    BFS_INPUT_DEVICE / BFS_VALIDATE / BFS_VALIDATE_SYMMETRY / BFS_ROWPTR32.
+ *   flags    BFS_INPUT_DEVICE / BFS_VALIDATE / BFS_VALIDATE_SYMMETRY / BFS_ROWPTR32 /
+ *            BFS_SORT_NEIGHBORS.
  *   out      receives the handle.
  * The library copies the arrays (host inputs by default) to the current HIP
  * device and owns the copies until bfs_destroy_graph; the caller may free

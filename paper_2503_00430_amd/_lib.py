@@ -17,6 +17,7 @@ BFS_INPUT_DEVICE = 0x1
 BFS_VALIDATE = 0x2
 BFS_VALIDATE_SYMMETRY = 0x4
 BFS_ROWPTR32 = 0x8
+BFS_SORT_NEIGHBORS = 0x10
 
 BFS_POLICY_AUTO = 0
 BFS_POLICY_ALPHA_BETA = 1

@@ -32,7 +32,7 @@ DEFAULT_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_p
 SINGLE_SPACE = {
     "alpha": [4, 8, 14, 30, 60, 120],
     "beta": [6, 12, 24, 48, 100],
-    "bu_wave_degree": [16, 32, 64, 128, 256],
+    "bu_wave_degree": [64, 256, 1024, 2048, 4096],
     "td_wave_degree": [8, 16, 32, 64],
     "td_block_degree": [512, 1024, 2048, 4096],
     "block_size": [256, 512, 1024],
@@ -156,6 +156,8 @@ def main(argv=None):
     ap.add_argument("--sources", type=int, default=16)
     ap.add_argument("--modes", default="single,batch")
     ap.add_argument("--out", default=DEFAULT_FILE)
+    ap.add_argument("--flags", type=lambda x: int(x, 0), default=L.BFS_SORT_NEIGHBORS,
+                    help="bfs_create_graph flags of the graphs the parameters are for")
     args = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
@@ -171,7 +173,7 @@ def main(argv=None):
     else:
         raise SystemExit(f"unknown workload {w}")
     srcs = graphgen.sources(cg, args.sources)
-    g = L.bfs_create_graph(cg.row_ptr, cg.col_idx)
+    g = L.bfs_create_graph(cg.row_ptr, cg.col_idx, args.flags)
     info = L.bfs_graph_info_get(g)
     tuned = {}
     for mode in args.modes.split(","):

@@ -142,7 +142,7 @@ static bfs_params default_params() {
   p.beta = 24;
   p.td_wave_degree = 32;
   p.td_block_degree = 2048;
-  p.bu_wave_degree = 64;
+  p.bu_wave_degree = 2048;
   p.block_size = 512;
   p.loop = BFS_LOOP_AUTO;
   p.graph_chunk_levels = 32;
@@ -199,7 +199,8 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     return fail(BFS_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
   if (nnz < 0) return fail(BFS_ERR_INVALID_ARG, "nnz < 0");
   if (!row_ptr || (nnz > 0 && !col_idx)) return fail(BFS_ERR_INVALID_ARG, "null CSR array");
-  if (flags & ~(BFS_INPUT_DEVICE | BFS_VALIDATE | BFS_VALIDATE_SYMMETRY | BFS_ROWPTR32))
+  if (flags & ~(BFS_INPUT_DEVICE | BFS_VALIDATE | BFS_VALIDATE_SYMMETRY | BFS_ROWPTR32 |
+                BFS_SORT_NEIGHBORS))
     return fail(BFS_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   const bool rp32 = flags & BFS_ROWPTR32;
   if (rp32 && nnz >= ((int64_t)1 << 31))
@@ -300,8 +301,11 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     int rc = alloc_single_scratch(g);
     if (rc) return bail(rc);
   }
-  e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault);
+  e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) return bail(fail(BFS_ERR_OUT_OF_MEMORY, "pinned allocation failed"));
+  std::memset(g->ctl_host, 0, sizeof(Ctl));
+  e = hipHostGetDevicePointer((void **)&g->ctl_host_dev, g->ctl_host, 0);
+  if (e != hipSuccess) return bail(fail(BFS_ERR_DEVICE, "hipHostGetDevicePointer failed"));
 
   // Copies.
   const hipMemcpyKind kind = (flags & BFS_INPUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -324,6 +328,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     return bail(fail(BFS_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(e)));
   {
     int rc = build_head(g);
+    if (!rc && (flags & BFS_SORT_NEIGHBORS)) rc = sort_neighbors_by_degree(g);
     if (rc) return bail(rc);
   }
   *out = g;

@@ -54,6 +54,9 @@ struct alignas(256) Ctl {
   unsigned int pad1;
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
+  Ctl *mirror;      // host-mapped copy the decide step publishes after every level
+  uint32_t seq;     // publications so far (the mirror's copy is written last)
+  uint32_t pad2;
 };
 
 // Level kernels run at most kMaxBlocks workgroups; each writes its counts
@@ -108,7 +111,8 @@ struct bfs_graph {
   uint64_t *ql[2] = {nullptr, nullptr};
   int64_t ql_cap = 0;
   bfsmi::Ctl *ctl = nullptr;
-  bfsmi::Ctl *ctl_host = nullptr;  // pinned mirror
+  bfsmi::Ctl *ctl_host = nullptr;  // pinned, coherent, device-mapped mirror of ctl
+  bfsmi::Ctl *ctl_host_dev = nullptr;  // its device-side address
   unsigned long long *partials = nullptr;
   bfsmi::LevelRec *recs = nullptr;
   int32_t rec_cap = 0;
@@ -154,6 +158,7 @@ struct DeviceGuard {
 
 int resolved_policy(const bfs_graph *g);
 int build_head(bfs_graph *g);  // fills g->head from the resident CSR
+int sort_neighbors_by_degree(bfs_graph *g);  // BFS_SORT_NEIGHBORS (reorder.hip)
 int alloc_single_scratch(bfs_graph *g);  // (re)allocates the large-vertex queues
 void release_graph_exec(bfs_graph *g);
 

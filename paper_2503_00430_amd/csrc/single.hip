@@ -202,6 +202,22 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   __syncthreads();
 }
 
+// Copies the control block to its host-mapped mirror, then bumps the
+// mirror's sequence number (system-scope release), so a host thread polling
+// that number sees a complete level state.  One thread.
+__device__ void publish(Ctl *c) {
+  Ctl *m = c->mirror;
+  if (!m) return;
+  const uint32_t seq = c->seq + 1;
+  c->seq = seq;
+  const uint64_t *src = reinterpret_cast<const uint64_t *>(c);
+  uint64_t *dst = reinterpret_cast<uint64_t *>(m);
+  constexpr int kWords = (int)(offsetof(Ctl, seq) / sizeof(uint64_t));
+  for (int i = 0; i < kWords; ++i) dst[i] = src[i];
+  __threadfence_system();
+  __hip_atomic_store(&m->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation: dist = -1, parent = -1, visited = isolated-vertex mask,
 // both frontier bitmaps and the partial counts cleared, then the source at
@@ -210,7 +226,7 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
 
 template <class RowT>
 __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
-                       int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap) {
+                       int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap, Ctl *mirror) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = tid; i < G.n; i += stride) {
@@ -259,6 +275,9 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->dist = dist;
     c->parent = parent;
     c->blocks_done = 0;
+    c->mirror = mirror;
+    c->seq = 0;
+    publish(c);
   }
 }
 
@@ -295,6 +314,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   if (found == 0) {
     c->done = 1;
     c->conv = kConvNone;
+    publish(c);
     return;
   }
   const int64_t m_u = c->m_u - fdeg;
@@ -316,10 +336,15 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   c->m_u = m_u;
   c->dir = nxt;
   c->level = L + 1;
+  publish(c);
 }
 
 // Reduces (and clears) the partial counts of `nblocks` workgroups; every
 // thread of the calling workgroup takes part, thread 0 receives the totals.
+// `same_kernel`: the partials were written by other workgroups of the
+// running kernel (read them with device-scope atomics); otherwise by an
+// earlier kernel (plain loads suffice).
+template <bool same_kernel>
 __device__ void reduce_partials(unsigned long long *partials, int nblocks, unsigned long long (&tot)[kPartials]) {
   __shared__ unsigned long long red[kPartials][16];
   unsigned long long v[kPartials] = {0, 0, 0, 0};
@@ -327,8 +352,13 @@ __device__ void reduce_partials(unsigned long long *partials, int nblocks, unsig
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
       unsigned long long *p = partials + (size_t)i * kPartials + k;
-      v[k] += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (same_kernel) {
+        v[k] += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        v[k] += *p;
+        *p = 0;
+      }
     }
   }
 #pragma unroll
@@ -463,7 +493,7 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
     if (last) {
       __threadfence();
       unsigned long long tot[kPartials];
-      reduce_partials(G.partials, gridDim.x, tot);
+      reduce_partials<true>(G.partials, gridDim.x, tot);
       if (threadIdx.x == 0) {
         G.ctl->blocks_done = 0;
         decide_apply(G.ctl, G.recs, tot);
@@ -684,7 +714,7 @@ __global__ void k_bu(DevG<RowT> G) {
 // Separate decide step: one workgroup after the level's kernels.
 __global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigned long long *partials) {
   unsigned long long tot[kPartials];
-  reduce_partials(partials, kMaxBlocks, tot);
+  reduce_partials<false>(partials, kMaxBlocks, tot);
   if (threadIdx.x != 0 || c->done) return;
   decide_apply(c, recs, tot);
 }
@@ -843,6 +873,25 @@ int read_ctl(bfs_graph *g, hipStream_t st) {
   return BFS_OK;
 }
 
+// Waits until the device has published level state number `seq` in the
+// host-mapped mirror (polling; the stream is checked now and then so that a
+// device error ends the wait), then copies it to *out.
+int wait_published(bfs_graph *g, hipStream_t st, uint32_t seq, Ctl *out) {
+  volatile uint32_t *p = &g->ctl_host->seq;
+  for (uint64_t spin = 0;; ++spin) {
+    if (__atomic_load_n(p, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 1023) == 1023) {
+      const hipError_t q = hipStreamQuery(st);
+      if (q != hipSuccess && q != hipErrorNotReady)
+        return fail(BFS_ERR_DEVICE, "level kernels failed: %s", hipGetErrorString(q));
+      if (q == hipSuccess && __atomic_load_n(p, __ATOMIC_ACQUIRE) != seq)
+        return fail(BFS_ERR_DEVICE, "the device did not publish level %u", seq);
+    }
+  }
+  std::memcpy(out, g->ctl_host, sizeof(Ctl));
+  return BFS_OK;
+}
+
 hipEvent_t level_event(bfs_graph *g, size_t i) {
   while (g->level_events.size() <= i) {
     hipEvent_t e = nullptr;
@@ -860,9 +909,10 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
   const bool timing = g->params.collect_timing != 0;
   int rc;
   size_t nev = 0;
-  for (;;) {
-    if ((rc = read_ctl(g, st))) return rc;
-    const Ctl h = *g->ctl_host;
+  uint32_t seq = 1;  // the init kernel published number 1
+  for (;; ++seq) {
+    Ctl h;
+    if ((rc = wait_published(g, st, seq, &h))) return rc;
     if (h.done) break;
     if (h.conv == kConvQ2B) {
       const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
@@ -964,7 +1014,7 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   BFS_HIP(hipEventRecord(g->ev_start, st));
   hipLaunchKernelGGL(k_init<RowT>, dim3(blocks_for(std::max(g->n, g->words), bs, 4096)), dim3(bs), 0, st,
                      G, s, dist, parent, (int32_t)policy, g->params.alpha, g->params.beta, g->nnz,
-                     g->rec_cap);
+                     g->rec_cap, g->ctl_host_dev);
   BFS_HIP(hipGetLastError());
   std::vector<float> level_ms;
   int rc = (loop == BFS_LOOP_HOST) ? host_loop(g, G, st, level_ms) : graph_loop(g, G, st, policy);

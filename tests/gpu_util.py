@@ -40,10 +40,22 @@ def gpu_bfs(gh, s, parent=True):
     return dist.cpu().numpy(), (par.cpu().numpy() if parent else None)
 
 
-def check_single(g, gh, s, *, parent=True, ref=None, full_validate=True, check_levels=True):
+def hub_first(g):
+    """The CSR with every row ordered by descending neighbour degree, ties by
+    ascending id (the order BFS_SORT_NEIGHBORS gives the device copy)."""
+    import graphgen
+    deg = np.diff(g.row_ptr)
+    rows = np.repeat(np.arange(g.n), deg)
+    order = np.lexsort((g.col_idx, -deg[g.col_idx], rows))
+    return graphgen.CSR(row_ptr=g.row_ptr.copy(), col_idx=g.col_idx[order].copy())
+
+
+def check_single(g, gh, s, *, parent=True, ref=None, full_validate=True, check_levels=True,
+                 scan_order=None):
     """Runs one search and checks it against the oracle:
     dist bit-exact; parents valid; per-level frontier sizes, direction
-    schedule and bottom-up work exactly as the oracle's replay."""
+    schedule and bottom-up work exactly as the oracle's replay (on
+    `scan_order`, the CSR in the order the device examines neighbours)."""
     bfs = library()
     d, p = gpu_bfs(gh, s, parent)
     od = ref if ref is not None else oracle.bfs(g, s, want_parent=False)[0]
@@ -72,7 +84,7 @@ def check_single(g, gh, s, *, parent=True, ref=None, full_validate=True, check_l
             assert lv["discovered"] == nxt
             assert lv["unvisited_edges"] == int(st["mu"][L])
             if lv["direction"] == oracle.BU:
-                prof = oracle.bottom_up_profile(g, od, L)
+                prof = oracle.bottom_up_profile(scan_order or g, od, L)
                 assert lv["scanned"] == prof["unvisited"], (L, lv, prof)
                 assert lv["examined"] == prof["examined"], (L, lv, prof)
     return d, p, run, levels

@@ -10,7 +10,7 @@ import pytest
 import graphgen
 import oracle
 from tests import graphs
-from tests.gpu_util import check_single, gpu_bfs, library, say, upload
+from tests.gpu_util import check_single, gpu_bfs, hub_first, library, say, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -204,4 +204,26 @@ def test_urand(bfs):
     gh = upload(g)
     for s in graphgen.sources(g, 4):
         check_single(g, gh, s)
+    gh.close()
+
+
+@pytest.mark.parametrize("rp32", [False, True])
+def test_sorted_neighbours(bfs, rmat16, rp32):
+    """BFS_SORT_NEIGHBORS: distances unchanged; bottom-up work equals the
+    oracle's profile on the hub-first order."""
+    g = rmat16
+    say("rmat16 hub-first rows, rp32", rp32)
+    flags = bfs.BFS_SORT_NEIGHBORS | (bfs.BFS_ROWPTR32 if rp32 else 0)
+    gh = upload(g, flags)
+    order = hub_first(g)
+    for pol in (1, 2):
+        bfs.bfs_set_params(gh, policy=pol)
+        for s in graphgen.sources(g, 4, seed=123):
+            check_single(g, gh, s, scan_order=order)
+    gh.close()
+    # a graph with ties and isolated vertices
+    gr = graphs.random_graph(3000, 9000, 8)
+    gh = upload(gr, bfs.BFS_SORT_NEIGHBORS)
+    for s in (0, 1500, 2999):
+        check_single(gr, gh, s, scan_order=hub_first(gr))
     gh.close()
