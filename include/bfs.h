@@ -74,8 +74,12 @@ typedef enum bfs_policy {
 typedef enum bfs_loop {
   BFS_LOOP_AUTO = 0,  /* GRAPH for top-down-only runs, HOST otherwise */
   BFS_LOOP_HOST = 1,  /* host issues each level and reads the level counters back */
-  BFS_LOOP_GRAPH = 2  /* replay a captured hipGraph of `graph_chunk_levels` levels
+  BFS_LOOP_GRAPH = 2, /* replay a captured hipGraph of `graph_chunk_levels` levels
                          whose kernels test device-side direction / done flags */
+  BFS_LOOP_PERSISTENT = 3 /* top-down-only runs: one cooperative launch of
+                             `graph_td_blocks` workgroups runs every level,
+                             levels separated by a grid barrier (hybrid
+                             policies fall back to HOST) */
 } bfs_loop;
 
 /* Tunables.  bfs_default_params() fills defaults; zero fields passed to
@@ -96,7 +100,8 @@ typedef struct bfs_params {
   int32_t msbfs_block_size;   /* batched search: threads per workgroup (default 256) */
   int32_t msbfs_bu_percent;   /* batched search: a level runs bottom-up when its frontier
                                  edge count exceeds this percent of nnz (default 5) */
-  int32_t graph_td_blocks;    /* GRAPH loop: workgroups of the fixed top-down grid (default 128) */
+  int32_t graph_td_blocks;    /* GRAPH / PERSISTENT loops: workgroups of the fixed top-down grid
+                                 (default 128) */
   int32_t reserved[3];
 } bfs_params;
 

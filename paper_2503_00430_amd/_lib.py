@@ -27,6 +27,7 @@ BFS_POLICY_TD_ONLY = 3
 BFS_LOOP_AUTO = 0
 BFS_LOOP_HOST = 1
 BFS_LOOP_GRAPH = 2
+BFS_LOOP_PERSISTENT = 3
 
 BFS_REQ_QUEUED = 0
 BFS_REQ_RUNNING = 1

@@ -164,7 +164,7 @@ static int check_params(const bfs_params &p) {
   for (int bs : {p.block_size, p.msbfs_block_size})
     if (bs < 64 || bs > 1024 || bs % 64)
       return fail(BFS_ERR_INVALID_ARG, "block sizes must be multiples of 64 in [64, 1024]");
-  if (p.loop < BFS_LOOP_AUTO || p.loop > BFS_LOOP_GRAPH)
+  if (p.loop < BFS_LOOP_AUTO || p.loop > BFS_LOOP_PERSISTENT)
     return fail(BFS_ERR_INVALID_ARG, "unknown loop driver %d", p.loop);
   if (p.graph_chunk_levels < 1 || p.graph_chunk_levels > 4096)
     return fail(BFS_ERR_INVALID_ARG, "graph_chunk_levels must be in [1, 4096]");

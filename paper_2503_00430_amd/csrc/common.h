@@ -55,6 +55,8 @@ struct alignas(256) Ctl {
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
   Ctl *mirror;      // host-mapped copy the decide step publishes after every level
+  uint32_t bar_count;  // grid barrier of the persistent top-down kernel
+  uint32_t bar_gen;
   uint32_t seq;     // publications so far (the mirror's copy is written last)
   uint32_t pad2;
 };
@@ -113,6 +115,7 @@ struct bfs_graph {
   bfsmi::Ctl *ctl = nullptr;
   bfsmi::Ctl *ctl_host = nullptr;  // pinned, coherent, device-mapped mirror of ctl
   bfsmi::Ctl *ctl_host_dev = nullptr;  // its device-side address
+  uint32_t pub_seq = 0;  // last publication number (continues across runs)
   unsigned long long *partials = nullptr;
   bfsmi::LevelRec *recs = nullptr;
   int32_t rec_cap = 0;

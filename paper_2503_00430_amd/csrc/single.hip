@@ -226,7 +226,8 @@ __device__ void publish(Ctl *c) {
 
 template <class RowT>
 __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
-                       int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap, Ctl *mirror) {
+                       int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap, Ctl *mirror,
+                       uint32_t seq0) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = tid; i < G.n; i += stride) {
@@ -276,8 +277,10 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->parent = parent;
     c->blocks_done = 0;
     c->mirror = mirror;
-    c->seq = 0;
-    publish(c);
+    c->bar_count = 0;
+    c->bar_gen = 0;
+    c->seq = seq0;  // publication numbers continue across runs, so a stale
+    publish(c);     // mirror never matches the number a new run waits for
   }
 }
 
@@ -401,24 +404,45 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
 //                                 reading the row 64 neighbours at a time;
 //   the rest                      workgroup per t2-edge chunk of a larger
 //                                 vertex.
+// Level state a top-down level needs, read once per level.
+struct TdLevel {
+  int32_t qcur, level;
+  int64_t cnt[3];
+  int32_t *dist, *parent;
+};
+
+__device__ __forceinline__ TdLevel td_level_state(const Ctl *c) {
+  TdLevel t;
+  t.qcur = c->qcur;
+  t.level = c->level;
+  for (int b = 0; b < 3; ++b) t.cnt[b] = c->qcnt[t.qcur][b];
+  t.dist = c->dist;
+  t.parent = c->parent;
+  return t;
+}
+
+// One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
+//   [0, nb_small)                 thread per vertex of degree <= t1;
+//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
+//                                 reading the row 64 neighbours at a time;
+//   the rest                      workgroup per t2-edge chunk of a larger
+//                                 vertex.
+// Ends with the staged queue entries flushed and the workgroup's counts in
+// its partials slot.  All threads of the workgroup call it.
 template <class RowT>
-__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fused_decide) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kTD) return;
-  extern __shared__ __align__(16) char lds[];
-  const Stage S = stage_open(lds);
-  const int qc = c->qcur, qn = qc ^ 1;
-  const int32_t level = c->level;
-  int32_t *dist = c->dist;
-  int32_t *parent = c->parent;
+__device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, const Stage &S, int blk,
+                                         int nblk, int nb_small, int nb_med) {
+  const int qc = T.qcur, qn = qc ^ 1;
+  const int32_t level = T.level;
+  int32_t *dist = T.dist;
+  int32_t *parent = T.parent;
   const int lane = lane_id();
   const int wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
   unsigned long long nfound = 0, dfound = 0;
-  const int blk = blockIdx.x;
   // Every role iterates in workgroup-uniform rounds so that the staging
   // buffers can be flushed between rounds.
   if (blk < nb_small) {
-    const int64_t cnt = c->qcnt[qc][kSmall];
+    const int64_t cnt = T.cnt[kSmall];
     const int32_t *q = qc ? G.qs[1] : G.qs[0];
     const int64_t step = (int64_t)nb_small * blockDim.x;
     for (int64_t round = (int64_t)blk * blockDim.x; round < cnt; round += step) {
@@ -432,16 +456,46 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
         row0 = (int64_t)G.rp[u];  // issued together with the head load
       }
       const int64_t deg = h.x;
-      for (int64_t j = 0; __ballot(j < deg); ++j) {  // j is uniform across the wavefront
+      // The head neighbours are claimed together: their visited words, the
+      // claims and the new vertices' degrees are three rounds of independent
+      // requests instead of three per neighbour.
+      {
+        const int32_t x[3] = {h.y, h.z, h.w};
+        uint64_t w[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
+        bool win[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const uint64_t bit = x[k] >= 0 ? 1ull << (x[k] & 63) : 0ull;
+          win[k] = false;
+          if (x[k] >= 0 && !(w[k] & bit))
+            win[k] = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (x[k] >> 6)),
+                                (unsigned long long)bit) & bit);
+        }
+        int64_t dv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (win[k]) {
+            dist[x[k]] = level + 1;  // plain store: the claim made this lane the only writer
+            if (parent) parent[x[k]] = u;
+            nfound += 1;
+            dfound += (unsigned long long)dv[k];
+          }
+          wave_stage(G, S, qn, win[k], x[k], dv[k]);
+        }
+      }
+      for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
         const bool has = j < deg;
-        int32_t v = 0;
-        if (has) v = j == 0 ? h.y : j == 1 ? h.z : j == 2 ? h.w : G.col[row0 + j];
+        const int32_t v = has ? G.col[row0 + j] : 0;
         td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
       }
       stage_flush(G, S, qn, true);
     }
   } else if (blk < nb_small + nb_med) {
-    const int64_t cnt = c->qcnt[qc][kMedium];
+    const int64_t cnt = T.cnt[kMedium];
     const int32_t *q = qc ? G.qm[1] : G.qm[0];
     const int64_t waves = (int64_t)nb_med * wpb;
     for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < cnt; round += waves) {
@@ -459,9 +513,9 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
       stage_flush(G, S, qn, true);
     }
   } else {
-    const int64_t cnt = c->qcnt[qc][kLarge];
+    const int64_t cnt = T.cnt[kLarge];
     const uint64_t *q = qc ? G.ql[1] : G.ql[0];
-    const int64_t nbl = (int64_t)gridDim.x - nb_small - nb_med;
+    const int64_t nbl = (int64_t)nblk - nb_small - nb_med;
     for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
       const uint64_t e = q[i];
       const int32_t u = (int32_t)(uint32_t)e;
@@ -480,6 +534,15 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
   }
   stage_flush(G, S, qn);
   block_partials<2>(G, {nfound, dfound});
+}
+
+template <class RowT>
+__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fused_decide) {
+  const Ctl *c = G.ctl;
+  if (c->done || c->dir != kTD) return;
+  extern __shared__ __align__(16) char lds[];
+  const Stage S = stage_open(lds);
+  td_level(G, td_level_state(c), S, blockIdx.x, gridDim.x, nb_small, nb_med);
   if (fused_decide) {
     // The last workgroup to finish applies the decide step (saves a launch
     // per level when the grid is small).
@@ -499,6 +562,57 @@ __global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fus
         decide_apply(G.ctl, G.recs, tot);
       }
     }
+  }
+}
+
+// Persistent top-down search (top-down-only policies): every level of the
+// search in one cooperative launch.  Workgroups process a level, then meet
+// at a grid barrier; the last workgroup to arrive reduces the level's counts
+// and applies the decide step before releasing the others.  Cross-workgroup
+// data (queues, counts, control block) is ordered by agent-scope release
+// fences before arriving and acquire fences after leaving, and the level
+// state is read with device-scope atomic loads.
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class RowT>
+__global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb_small, int32_t nb_med) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int last;
+  Ctl *c = G.ctl;
+  for (int64_t it = 0; it <= G.n; ++it) {
+    if (__hip_atomic_load(&c->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;  // uniform
+    TdLevel T;
+    T.qcur = (int32_t)ld_agent(reinterpret_cast<const uint32_t *>(&c->qcur));
+    T.level = (int32_t)ld_agent(reinterpret_cast<const uint32_t *>(&c->level));
+    for (int b = 0; b < 3; ++b) T.cnt[b] = ld_agent(&c->qcnt[T.qcur][b]);
+    T.dist = c->dist;  // constant for the whole search
+    T.parent = c->parent;
+    const Stage S = stage_open(lds);
+    td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med);
+    // grid barrier; the last arrival decides.  Every wavefront releases its
+    // own stores (queue entries, partial counts) before the workgroup arrives.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&c->bar_count, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      unsigned long long tot[kPartials];
+      reduce_partials<true>(G.partials, gridDim.x, tot);
+      if (threadIdx.x == 0) {
+        decide_apply(c, G.recs, tot);
+        __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else if (threadIdx.x == 0) {
+      const uint32_t g0 = (uint32_t)it;  // generation number before this level's release
+      while (ld_agent(&c->bar_gen) == g0) __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
 }
 
@@ -640,67 +754,79 @@ __global__ void k_bu(DevG<RowT> G) {
     const uint64_t my_vis = lane < nwd ? G.vis[sr + lane] : ~0ull;
     W.mask[lane] = 0;
     unsigned rhead = 0, rcount = 0;  // deferred ring (wave-uniform)
-    // head records of the first word with unvisited vertices
-    int4 hn = make_int4(0, -1, -1, -1);
-    {
-      const uint64_t vw0 = __shfl(my_vis, 0);
-      if (vw0 != ~0ull && !((vw0 >> lane) & 1ull)) hn = G.head[sr * kWave + lane];
+    // Three-stage software pipeline over the run's words: while word k is
+    // resolved, the frontier words of word k+1's head neighbours and the
+    // head records of word k+2 are already in flight.
+    auto load_head = [&](int k) {
+      const uint64_t vwk = __shfl(my_vis, k);
+      return (vwk != ~0ull && !((vwk >> lane) & 1ull)) ? G.head[(sr + k) * kWave + lane]
+                                                      : make_int4(0, -1, -1, -1);
+    };
+    uint64_t fa0 = 0, fa1 = 0, fa2 = 0;
+    auto load_front = [&](const int4 &hh) {
+      fa0 = hh.y >= 0 ? front[hh.y >> 6] : 0ull;
+      fa1 = hh.z >= 0 ? front[hh.z >> 6] : 0ull;
+      fa2 = hh.w >= 0 ? front[hh.w >> 6] : 0ull;
+    };
+    int4 ha = load_head(0);
+    load_front(ha);
+    int4 hb = nwd > 1 ? load_head(1) : make_int4(0, -1, -1, -1);
+    // k == nwd is an extra pass that only drains what is left in the ring
+    for (int k = 0; k <= nwd; ++k) {
+      if (k < nwd) {
+        const uint64_t vw = __shfl(my_vis, k);
+        const int4 h = ha;
+        const uint64_t f0 = fa0, f1 = fa1, f2 = fa2;
+        if (k + 1 < nwd) {
+          load_front(hb);
+          ha = hb;
+        }
+        if (k + 2 < nwd) hb = load_head(k + 2);
+        if (vw != ~0ull) {
+          const int64_t v = (sr + k) * kWave + lane;  // ids >= n are marked visited in vw
+          const bool unvisited = !((vw >> lane) & 1ull);
+          bool found = false, defer = false;
+          int32_t hit = -1;
+          if (unvisited) {
+            const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
+            int64_t ex = h.x;
+            if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
+              found = true; hit = x0; ex = 1;
+            } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
+              found = true; hit = x1; ex = 2;
+            } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
+              found = true; hit = x2; ex = 3;
+            } else if (h.x > 3) {
+              defer = true;  // counted when its row is scanned
+            }
+            if (!defer) nexam += (unsigned long long)ex;
+            nscan += 1;
+            if (found) {
+              dist[v] = level + 1;
+              if (parent) parent[v] = hit;
+              nfound += 1;
+              dfound += (unsigned long long)h.x;
+            }
+          }
+          const uint64_t fm = __ballot(found);
+          if (lane == 0 && fm) W.mask[k] = fm;
+          const uint64_t dm = __ballot(defer);
+          if (defer) {
+            const unsigned slot = (rhead + rcount + lanes_below(dm)) % kRing;
+            W.v[slot] = (int32_t)v;
+            W.deg[slot] = h.x;
+            W.word[slot] = (uint8_t)k;
+          }
+          rcount += (unsigned)__popcll(dm);
+        }
+      }
+      if (rcount >= kWave || (k == nwd && rcount > 0)) {  // uniform
+        const unsigned cnt = rcount < kWave ? rcount : kWave;
+        bu_drain(G, W, rhead, cnt, front, sr, level, dist, parent, nfound, dfound, nexam);
+        rhead = (rhead + cnt) % kRing;
+        rcount -= cnt;
+      }
     }
-    for (int k = 0; k < nwd; ++k) {
-      const uint64_t vw = __shfl(my_vis, k);
-      const int4 h = hn;
-      if (k + 1 < nwd) {  // prefetch the next word's head records
-        const uint64_t vw1 = __shfl(my_vis, k + 1);
-        if (vw1 != ~0ull && !((vw1 >> lane) & 1ull)) hn = G.head[(sr + k + 1) * kWave + lane];
-      }
-      if (vw == ~0ull) continue;
-      const int64_t v = (sr + k) * kWave + lane;  // ids >= n are marked visited in vw
-      const bool unvisited = !((vw >> lane) & 1ull);
-      bool found = false, defer = false;
-      int32_t hit = -1;
-      if (unvisited) {
-        const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
-        const uint64_t f0 = x0 >= 0 ? front[x0 >> 6] : 0ull;
-        const uint64_t f1 = x1 >= 0 ? front[x1 >> 6] : 0ull;
-        const uint64_t f2 = x2 >= 0 ? front[x2 >> 6] : 0ull;
-        int64_t ex = h.x;
-        if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
-          found = true; hit = x0; ex = 1;
-        } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
-          found = true; hit = x1; ex = 2;
-        } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
-          found = true; hit = x2; ex = 3;
-        } else if (h.x > 3) {
-          defer = true;  // counted when its row is scanned
-        }
-        if (!defer) nexam += (unsigned long long)ex;
-        nscan += 1;
-        if (found) {
-          dist[v] = level + 1;
-          if (parent) parent[v] = hit;
-          nfound += 1;
-          dfound += (unsigned long long)h.x;
-        }
-      }
-      const uint64_t fm = __ballot(found);
-      if (lane == 0 && fm) W.mask[k] = fm;
-      const uint64_t dm = __ballot(defer);
-      if (dm) {
-        if (defer) {
-          const unsigned slot = (rhead + rcount + lanes_below(dm)) % kRing;
-          W.v[slot] = (int32_t)v;
-          W.deg[slot] = h.x;
-          W.word[slot] = (uint8_t)k;
-        }
-        rcount += (unsigned)__popcll(dm);
-        if (rcount >= kWave) {
-          bu_drain(G, W, rhead, kWave, front, sr, level, dist, parent, nfound, dfound, nexam);
-          rhead = (rhead + kWave) % kRing;
-          rcount -= kWave;
-        }
-      }
-    }
-    if (rcount) bu_drain(G, W, rhead, rcount, front, sr, level, dist, parent, nfound, dfound, nexam);
     // one coalesced store of the run's next-frontier and visited words
     if (lane < nwd) {
       const uint64_t m = W.mask[lane];
@@ -909,10 +1035,24 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
   const bool timing = g->params.collect_timing != 0;
   int rc;
   size_t nev = 0;
-  uint32_t seq = 1;  // the init kernel published number 1
+  // Level 0 is known without asking the device: top-down from the source
+  // alone (its degree class is not known here, so every role gets a
+  // workgroup; the kernel reads the exact counts).  Publication base + 1 is
+  // the init kernel's, base + L + 2 the state after level L.
+  const uint32_t base = g->pub_seq;
+  uint32_t seq = base + 1;
   for (;; ++seq) {
     Ctl h;
-    if ((rc = wait_published(g, st, seq, &h))) return rc;
+    if (seq == base + 1) {
+      std::memset(&h, 0, sizeof(h));
+      h.dir = kTD;
+      h.conv = kConvNone;
+      h.qcnt[0][kSmall] = 1;
+      h.qcnt[0][kMedium] = 1;
+      h.qcnt[0][kLarge] = g->max_degree > G.t2 ? (unsigned)((g->max_degree + G.t2 - 1) / G.t2) : 0;
+    } else if ((rc = wait_published(g, st, seq, &h))) {
+      return rc;
+    }
     if (h.done) break;
     if (h.conv == kConvQ2B) {
       const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
@@ -1002,6 +1142,31 @@ int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
   return BFS_OK;
 }
 
+// Persistent top-down loop: one cooperative launch runs every level.
+template <class RowT>
+int persistent_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st) {
+  const Shapes S = shapes_of(g);
+  const int nb = g->params.graph_td_blocks;
+  int per_cu = 0, cus = 0;
+  BFS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_td_persistent<RowT>, S.bs, S.lds));
+  BFS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  const int blocks = std::max(1, std::min(nb, per_cu * cus));
+  // role split of the fixed grid, by the degree classes the graph has
+  // (every class the graph has gets at least one workgroup)
+  const int classes = g->max_degree > G.t2 ? 3 : g->max_degree > G.t1 ? 2 : 1;
+  if (blocks < classes)
+    return fail(BFS_ERR_INVALID_ARG, "graph_td_blocks = %d is below the %d degree classes of this graph",
+                blocks, classes);
+  const int nb_med = classes >= 2 ? std::max(1, blocks / 4) : 0;
+  const int nb_large = classes == 3 ? std::max(1, blocks / 4) : 0;
+  const int nb_small = blocks - nb_med - nb_large;
+  int32_t a_small = nb_small, a_med = nb_med;
+  void *args[] = {const_cast<DevG<RowT> *>(&G), &a_small, &a_med};
+  BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_td_persistent<RowT>), dim3(blocks),
+                                     dim3(S.bs), args, S.lds, st));
+  return read_ctl(g, st);
+}
+
 template <class RowT>
 int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1010,21 +1175,29 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   const int policy = resolved_policy(g);
   int loop = g->params.loop;
   if (loop == BFS_LOOP_AUTO) loop = (policy == BFS_POLICY_TD_ONLY) ? BFS_LOOP_GRAPH : BFS_LOOP_HOST;
+  if (loop == BFS_LOOP_PERSISTENT && policy != BFS_POLICY_TD_ONLY) loop = BFS_LOOP_HOST;
   const int bs = g->params.block_size;
+  g->pub_seq = std::max(g->pub_seq, __atomic_load_n(&g->ctl_host->seq, __ATOMIC_ACQUIRE));
   BFS_HIP(hipEventRecord(g->ev_start, st));
   hipLaunchKernelGGL(k_init<RowT>, dim3(blocks_for(std::max(g->n, g->words), bs, 4096)), dim3(bs), 0, st,
                      G, s, dist, parent, (int32_t)policy, g->params.alpha, g->params.beta, g->nnz,
-                     g->rec_cap, g->ctl_host_dev);
+                     g->rec_cap, loop == BFS_LOOP_HOST ? g->ctl_host_dev : nullptr, g->pub_seq);
   BFS_HIP(hipGetLastError());
   std::vector<float> level_ms;
-  int rc = (loop == BFS_LOOP_HOST) ? host_loop(g, G, st, level_ms) : graph_loop(g, G, st, policy);
-  if (rc) return rc;
+  int rc = loop == BFS_LOOP_HOST    ? host_loop(g, G, st, level_ms)
+           : loop == BFS_LOOP_GRAPH ? graph_loop(g, G, st, policy)
+                                    : persistent_loop(g, G, st);
+  if (rc) {
+    g->pub_seq += 1u << 20;  // keep later runs clear of anything this run may still publish
+    return rc;
+  }
   BFS_HIP(hipEventRecord(g->ev_stop, st));
   BFS_HIP(hipEventSynchronize(g->ev_stop));
   const auto t1 = std::chrono::steady_clock::now();
   float dev_ms = 0.f;
   BFS_HIP(hipEventElapsedTime(&dev_ms, g->ev_start, g->ev_stop));
   const Ctl h = *g->ctl_host;  // final state (read by the loop after the last level)
+  g->pub_seq = h.seq;
   const int nrec = std::min(h.levels_done, g->rec_cap);
   std::vector<LevelRec> recs(nrec);
   if (nrec > 0)

@@ -24,7 +24,7 @@ def bfs():
 
 @pytest.mark.parametrize("name", sorted(graphs.CLOSED_FORMS))
 @pytest.mark.parametrize("policy", sorted(POLICIES))
-@pytest.mark.parametrize("loop", [1, 2])
+@pytest.mark.parametrize("loop", [1, 2, 3])
 def test_closed_forms(bfs, name, policy, loop):
     g, f = graphs.CLOSED_FORMS[name]()
     say("closed form", name, policy, "loop", loop)
@@ -124,7 +124,7 @@ def test_edge_cases(bfs):
     gh.close()
 
 
-@pytest.mark.parametrize("loop", [1, 2])
+@pytest.mark.parametrize("loop", [1, 2, 3])
 def test_hub_chunks(bfs, loop):
     """A hub of degree 50 000 (far above td_block_degree) as source and as a
     discovered vertex: its row is split into workgroup chunks."""
@@ -194,7 +194,7 @@ def test_grid_small_many_sources(bfs):
     gh = upload(g)
     for s in graphgen.sources(g, 8):
         _, _, run, _ = check_single(g, gh, s)
-        assert run["policy"] == 3 and run["loop"] == 2
+        assert run["policy"] == 3 and run["loop"] == bfs.BFS_LOOP_GRAPH
     gh.close()
 
 
@@ -226,4 +226,26 @@ def test_sorted_neighbours(bfs, rmat16, rp32):
     gh = upload(gr, bfs.BFS_SORT_NEIGHBORS)
     for s in (0, 1500, 2999):
         check_single(gr, gh, s, scan_order=hub_first(gr))
+    gh.close()
+
+
+@pytest.mark.parametrize("blocks", [1, 2, 3, 16, 128, 512])
+def test_persistent_loop_grid_sizes(bfs, rmat16, blocks):
+    """The persistent top-down loop with grids from one workgroup upward, on a
+    long path (thousands of levels) and on RMAT (every degree class)."""
+    say("persistent loop, blocks", blocks)
+    g, f = graphs.path(2500)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, loop=3, policy=3, graph_td_blocks=blocks)
+    _, _, run, _ = check_single(g, gh, 7, ref=f(7).astype(np.int32))
+    assert run["loop"] == 3
+    gh.close()
+    gh = upload(rmat16)
+    bfs.bfs_set_params(gh, loop=3, policy=3, graph_td_blocks=blocks, td_block_degree=256)
+    if blocks < 3:
+        with pytest.raises(bfs.BfsError):  # three degree classes need three roles
+            gpu_bfs(gh, int(graphgen.sources(rmat16, 1)[0]))
+    else:
+        for s in graphgen.sources(rmat16, 2, seed=5):
+            check_single(rmat16, gh, s)
     gh.close()
