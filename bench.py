@@ -8,10 +8,11 @@ undirected edges of the source's component and t_s the median wall time of
 its bfs_run call over the timed steps; `value` is their harmonic mean.  The
 graph is resident in HBM before timing starts.  Prints one JSON line.
 
-The dominant kernel is the bottom-up level kernel: its average duration is
-taken from HIP events recorded around every bottom-up launch in the timed
-steps, and its algorithmic bytes per launch from the byte model (visited,
-row-offset, neighbour-id, frontier and output bytes the level must move).
+The dominant kernel is the level kernel in its bottom-up instance
+(k_level<RowT, 1>): its average duration is taken from HIP events recorded
+around every bottom-up launch in the timed steps, and its algorithmic bytes
+per launch from the byte model (visited, row-offset, neighbour-id, frontier
+and output bytes the level must move).
 """
 from __future__ import annotations
 
@@ -72,7 +73,7 @@ def kernel_hash():
 def measured_traffic(workload):
     """HBM bytes per bottom-up launch from the committed rocprofv3 counter
     summary, or None when it is absent or the kernel source has changed."""
-    path = os.path.join(ROOT, "profiles", f"k_bu_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_level_bu_{workload}_traffic.json")
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
@@ -363,7 +364,8 @@ def main():
         achieved = avg_bytes / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(args.workload), "kernel": "k_bu",
+                    "traffic": measured_traffic(args.workload),
+                    "kernel": "k_level<long, 1> (bottom-up instance)",
                     "avg_launch_us": round(avg_s * 1e6, 2),
                     "algo_bytes_per_launch": int(avg_bytes), "launches": len(bu_levels)}
     # per-level profile of the first source (stderr, for reading)

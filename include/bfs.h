@@ -102,7 +102,10 @@ typedef struct bfs_params {
                                  edge count exceeds this percent of nnz (default 5) */
   int32_t graph_td_blocks;    /* GRAPH / PERSISTENT loops: workgroups of the fixed top-down grid
                                  (default 128) */
-  int32_t reserved[3];
+  int32_t bu_blocks;          /* bottom-up: workgroups of the grid, each wavefront taking an equal
+                                 share of the visited words (0 = automatic: one word per
+                                 wavefront up to 1024 workgroups; at most 1024) */
+  int32_t reserved[2];
 } bfs_params;
 
 /* One record per executed level of the last bfs_run on a graph. */

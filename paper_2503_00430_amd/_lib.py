@@ -42,7 +42,7 @@ class bfs_params(ctypes.Structure):
     _fields_ = [(name, _i32) for name in (
         "policy", "alpha", "beta", "td_wave_degree", "td_block_degree", "bu_wave_degree",
         "block_size", "loop", "graph_chunk_levels", "collect_timing", "msbfs_block_size",
-        "msbfs_bu_percent", "graph_td_blocks")] + [("reserved", _i32 * 3)]
+        "msbfs_bu_percent", "graph_td_blocks", "bu_blocks")] + [("reserved", _i32 * 2)]
 
 
 class bfs_level_stats(ctypes.Structure):

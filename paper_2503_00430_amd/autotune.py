@@ -36,6 +36,7 @@ SINGLE_SPACE = {
     "td_wave_degree": [8, 16, 32, 64],
     "td_block_degree": [512, 1024, 2048, 4096],
     "block_size": [256, 512, 1024],
+    "bu_blocks": [0, 256, 512],
 }
 GRAPH_SPACE = {
     "graph_td_blocks": [16, 32, 64, 128, 256],

@@ -170,6 +170,8 @@ static int check_params(const bfs_params &p) {
     return fail(BFS_ERR_INVALID_ARG, "graph_chunk_levels must be in [1, 4096]");
   if (p.graph_td_blocks < 1 || p.graph_td_blocks > 512)
     return fail(BFS_ERR_INVALID_ARG, "graph_td_blocks must be in [1, 512]");
+  if (p.bu_blocks < 0 || p.bu_blocks > kMaxBlocks)
+    return fail(BFS_ERR_INVALID_ARG, "bu_blocks must be in [0, %d]", kMaxBlocks);
   if (p.msbfs_bu_percent < 0 || p.msbfs_bu_percent > 100)
     return fail(BFS_ERR_INVALID_ARG, "msbfs_bu_percent must be in [0, 100]");
   return BFS_OK;
@@ -293,7 +295,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     ALLOC(g->qm[s], n);
   }
   ALLOC(g->ctl, 1);
-  ALLOC(g->partials, (size_t)kMaxBlocks * kPartials);
+  ALLOC(g->partials, kPartialsAlloc);
   g->rec_cap = 1 << 16;
   ALLOC(g->recs, g->rec_cap);
 #undef ALLOC
@@ -319,7 +321,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   if (e == hipSuccess && nnz > 0) e = hipMemcpy(g->col, col_idx, sizeof(int32_t) * nnz, kind);
   if (e == hipSuccess) e = hipMemcpy(g->iso, iso.data(), sizeof(uint64_t) * g->words, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(g->ctl, 0, sizeof(Ctl));
-  if (e == hipSuccess) e = hipMemset(g->partials, 0, sizeof(unsigned long long) * kMaxBlocks * kPartials);
+  if (e == hipSuccess) e = hipMemset(g->partials, 0, sizeof(unsigned long long) * kPartialsAlloc);
   if (e == hipSuccess) e = hipEventCreate(&g->ev_start);
   if (e == hipSuccess) e = hipEventCreate(&g->ev_stop);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);

@@ -19,6 +19,7 @@ constexpr int kWave = 64;
 enum Dir : int32_t { kTD = 0, kBU = 1 };
 enum Conv : int32_t { kConvNone = 0, kConvQ2B = 1, kConvB2Q = 2 };
 enum Bucket : int32_t { kSmall = 0, kMedium = 1, kLarge = 2 };
+enum Publish : int32_t { kPubEvery = 0, kPubFinal = 1 };
 
 // Per-level record written on the device by the decide step.
 struct LevelRec {
@@ -50,15 +51,14 @@ struct alignas(256) Ctl {
   int64_t sum_mf;   // sum of m_f over all levels so far (= 2 * TEPS edge count)
   int64_t reached;  // vertices visited so far
   unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
-  unsigned int blocks_done;  // workgroups of the running level that have finished
-  unsigned int pad1;
+  unsigned int pad1[2];
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
   Ctl *mirror;      // host-mapped copy the decide step publishes after every level
   uint32_t bar_count;  // grid barrier of the persistent top-down kernel
   uint32_t bar_gen;
   uint32_t seq;     // publications so far (the mirror's copy is written last)
-  uint32_t pad2;
+  int32_t pub_mode; // kPubEvery: publish after every level; kPubFinal: only the last
 };
 
 // Level kernels run at most kMaxBlocks workgroups; each writes its counts
@@ -67,6 +67,14 @@ struct alignas(256) Ctl {
 // workgroups add to the same device word.
 constexpr int kMaxBlocks = 1024;
 constexpr int kPartials = 4;
+// The fused decide step's accumulators (kArriveGroups x kPartials) and
+// arrival counters (one per group and one over the groups) follow the
+// partials in the same allocation, each in its own 128-byte line.
+constexpr int kArriveGroups = 8;
+constexpr int kLineU64 = 16;
+constexpr size_t kAccOffset = (size_t)kMaxBlocks * kPartials;
+constexpr size_t kArriveOffset = kAccOffset + (size_t)kArriveGroups * kPartials * kLineU64;
+constexpr size_t kPartialsAlloc = kArriveOffset + (size_t)(kArriveGroups + 1) * kLineU64;
 
 // Everything a single-source kernel needs, passed by value.
 template <class RowT>
@@ -82,7 +90,7 @@ struct DevG {
   uint64_t *ql[2];      //             large-degree vertices, one entry per chunk: chunk << 32 | v
   Ctl *ctl;
   LevelRec *recs;
-  unsigned long long *partials;  // [kMaxBlocks][kPartials]
+  unsigned long long *partials;  // [kMaxBlocks][kPartials], then accumulators and arrivals
   int64_t n;
   int64_t words;        // 64-bit words per bitmap
   int32_t t1, t2, tbu;  // degree thresholds (td_wave_degree, td_block_degree, bu_wave_degree)

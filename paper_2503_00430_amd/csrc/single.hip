@@ -227,7 +227,7 @@ __device__ void publish(Ctl *c) {
 template <class RowT>
 __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
                        int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap, Ctl *mirror,
-                       uint32_t seq0) {
+                       uint32_t seq0, int32_t pub_mode) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = tid; i < G.n; i += stride) {
@@ -241,7 +241,7 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     G.bm[0][w] = 0;
     G.bm[1][w] = 0;
   }
-  for (int64_t i = tid; i < (int64_t)kMaxBlocks * kPartials; i += stride) G.partials[i] = 0;
+  for (int64_t i = tid; i < (int64_t)kPartialsAlloc; i += stride) G.partials[i] = 0;  // and arrivals
   if (tid == 0) {
     Ctl *c = G.ctl;
     const int64_t deg = (int64_t)G.rp[s + 1] - (int64_t)G.rp[s];
@@ -275,7 +275,7 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     }
     c->dist = dist;
     c->parent = parent;
-    c->blocks_done = 0;
+    c->pub_mode = pub_mode;
     c->mirror = mirror;
     c->bar_count = 0;
     c->bar_gen = 0;
@@ -339,7 +339,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   c->m_u = m_u;
   c->dir = nxt;
   c->level = L + 1;
-  publish(c);
+  if (c->pub_mode == kPubEvery) publish(c);
 }
 
 // Reduces (and clears) the partial counts of `nblocks` workgroups; every
@@ -431,7 +431,8 @@ __device__ __forceinline__ TdLevel td_level_state(const Ctl *c) {
 // its partials slot.  All threads of the workgroup call it.
 template <class RowT>
 __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, const Stage &S, int blk,
-                                         int nblk, int nb_small, int nb_med) {
+                                         int nblk, int nb_small, int nb_med,
+                                         unsigned long long (&counts)[2]) {
   const int qc = T.qcur, qn = qc ^ 1;
   const int32_t level = T.level;
   int32_t *dist = T.dist;
@@ -533,36 +534,97 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     }
   }
   stage_flush(G, S, qn);
-  block_partials<2>(G, {nfound, dfound});
+  counts[0] = nfound;
+  counts[1] = dfound;
 }
 
-template <class RowT>
-__global__ void k_td(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t fused_decide) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kTD) return;
-  extern __shared__ __align__(16) char lds[];
-  const Stage S = stage_open(lds);
-  td_level(G, td_level_state(c), S, blockIdx.x, gridDim.x, nb_small, nb_med);
-  if (fused_decide) {
-    // The last workgroup to finish applies the decide step (saves a launch
-    // per level when the grid is small).
+// Launch options of the level kernel.
+enum LevelMode : int32_t {
+  kFusedDecide = 1  // the last workgroup applies the decide step
+};
+
+// End of a direction kernel: the workgroup's K counts reach the decide
+// step, either as this workgroup's slot of the partials array (a later
+// kernel reduces them) or, with kFusedDecide, through the fused decide step,
+// which needs no memory fence (a release fence at device scope writes back
+// the XCD's whole L2, far too costly once per workgroup):
+//   1. thread 0 adds the workgroup's counts to the accumulators of its group
+//      (blockIdx.x modulo kArriveGroups: consecutive workgroups go to
+//      different XCDs, so no accumulator takes more than a 1/kArriveGroups
+//      share) with device-scope atomics and waits for them to complete;
+//   2. it then arrives on its group's counter; the last arrival of a group
+//      arrives on the counter over the groups;
+//   3. the last arrival of all collects the totals by exchanging the
+//      accumulators with zero (completed atomics, so every count is there),
+//      resets the counters, and applies the decide step.
+// Small grids (at most kFenceDecideBlocks workgroups, so little data is
+// dirty per XCD) instead write the partials slot, release it with a fence and
+// arrive on one counter; the last arrival reduces the slots.  All threads of
+// the workgroup call it.
+constexpr int kFenceDecideBlocks = 64;
+
+template <int K, class RowT>
+__device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, const unsigned long long (&v)[K]) {
+  if (!(mode & kFusedDecide)) {
+    block_partials<K>(G, v);
+    return;
+  }
+  uint32_t *arrive = reinterpret_cast<uint32_t *>(G.partials + kArriveOffset);
+  constexpr int kLineU32 = 2 * kLineU64;
+  if (gridDim.x <= (unsigned)kFenceDecideBlocks) {
+    block_partials<K>(G, v);  // written by wave 0, whose fence below releases them
     __shared__ int last;
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
-      last = atomicAdd(&G.ctl->blocks_done, 1u) == gridDim.x - 1;
+      last = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u) == gridDim.x - 1;
+      if (last) atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
     }
     __syncthreads();
     if (last) {
       __threadfence();
       unsigned long long tot[kPartials];
       reduce_partials<true>(G.partials, gridDim.x, tot);
-      if (threadIdx.x == 0) {
-        G.ctl->blocks_done = 0;
-        decide_apply(G.ctl, G.recs, tot);
-      }
+      if (threadIdx.x == 0) decide_apply(G.ctl, G.recs, tot);
     }
+    return;
   }
+  __shared__ unsigned long long part[K][16];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const unsigned long long sum = wave_sum(v[k]);
+    if (lane_id() == 0) part[k][w] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  unsigned long long t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    t[k] = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t[k] += part[k][i];
+  }
+  unsigned long long *acc = G.partials + kAccOffset;
+  const unsigned nb = gridDim.x;
+  const unsigned grp = blockIdx.x % kArriveGroups;
+  const unsigned gsize = (nb - grp + kArriveGroups - 1) / kArriveGroups;
+  const unsigned ngroups = nb < (unsigned)kArriveGroups ? nb : (unsigned)kArriveGroups;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (t[k]) atomicAdd(&acc[(grp * kPartials + k) * kLineU64], t[k]);
+  // the adds must have completed before this workgroup is counted
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (atomicAdd(&arrive[grp * kLineU32], 1u) != gsize - 1) return;
+  atomicExch(&arrive[grp * kLineU32], 0u);
+  if (atomicAdd(&arrive[kArriveGroups * kLineU32], 1u) != ngroups - 1) return;
+  atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
+  unsigned long long tot[kPartials];
+#pragma unroll
+  for (int k = 0; k < kPartials; ++k) {
+    tot[k] = 0;
+    for (unsigned gi = 0; gi < ngroups; ++gi) tot[k] += atomicExch(&acc[(gi * kPartials + k) * kLineU64], 0ull);
+  }
+  decide_apply(G.ctl, G.recs, tot);
 }
 
 // Persistent top-down search (top-down-only policies): every level of the
@@ -590,7 +652,9 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
     const Stage S = stage_open(lds);
-    td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med);
+    unsigned long long counts[2];
+    td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med, counts);
+    block_partials<2>(G, counts);
     // grid barrier; the last arrival decides.  Every wavefront releases its
     // own stores (queue entries, partial counts) before the workgroup arrives.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -620,45 +684,59 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
 // frontier neighbour and stops at the first).  A wavefront owns a contiguous
 // run of 64-bit visited words (64 vertices each), taken 64 words at a time:
 //   1. the 64 visited words are loaded with one coalesced load (a lane each);
-//   2. word by word, each unvisited lane tests the three neighbours of its
-//      head record against the frontier bitmap; the next word's head records
-//      are prefetched while the current word is resolved;
-//   3. lanes that miss and have longer rows are deferred to a per-wavefront
-//      ring in LDS; whenever 64 have gathered, the wavefront scans those 64
-//      rows one per lane (kBuUnroll neighbours per step as independent
-//      loads), rows longer than tbu by the whole wavefront with a ballot
-//      early exit;
-//   4. the found masks collect in LDS and are written as next-frontier and
+//      words with no unvisited vertex are skipped without any other work;
+//   2. the unvisited vertices of the remaining words are compacted, in word
+//      order, into a per-wavefront candidate ring in LDS, so every lane of a
+//      batch holds a real candidate whatever the density of unvisited
+//      vertices (dense early levels and sparse late ones cost the same per
+//      candidate);
+//   3. each batch of 64 candidates loads its head records (degree and first
+//      three neighbours) and tests them against the frontier bitmap (the
+//      second and third only where the first misses); the next batch's head
+//      records are already in flight while a batch is resolved;
+//   4. candidates that miss and have longer rows go to a deferred ring; once
+//      64 have gathered, the wavefront scans those rows one per lane
+//      (kBuUnroll neighbours per step as independent loads), rows longer
+//      than tbu by the whole wavefront with a ballot early exit;
+//   5. the found masks collect in LDS and are written as next-frontier and
 //      visited words with one coalesced store per run.
 // `examined` counts neighbours up to and including the first hit.
-constexpr int kBuUnroll = 8;
-constexpr int kRing = 128;  // deferred rows per wavefront (at most 63 + 64 pending)
+constexpr int kBuUnroll = 4;
+constexpr int kCand = 128;  // candidate ring: < 64 waiting + 64 from one word
+constexpr int kDefer = 128;  // deferred ring: < 64 waiting + 64 from one batch
 
 struct BuWaveLds {
-  int32_t v[kRing];
-  int32_t deg[kRing];
-  uint8_t word[kRing];
+  int32_t cand[kCand];
+  int32_t dv[kDefer];
+  int32_t ddeg[kDefer];
   uint64_t mask[kWave];
 };
 
 __host__ __device__ constexpr size_t bu_lds_bytes(int bs) { return (size_t)(bs / kWave) * sizeof(BuWaveLds); }
 
+__device__ __forceinline__ bool front_bit(const uint32_t *front, int32_t x) {
+  return (front[x >> 5] >> (x & 31)) & 1u;
+}
+
+// Per-lane counters of a bottom-up level.
+struct BuCount {
+  unsigned long long found = 0, fdeg = 0, scan = 0, exam = 0;
+};
+
 // Scans `cnt` (<= 64) deferred rows starting at ring slot `head`, one per
-// lane; records the finds in the LDS masks.
+// lane (rows longer than tbu by the whole wavefront); records the finds.
 template <class RowT>
 __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsigned head, unsigned cnt,
-                                         const uint64_t *front, int64_t sr, int32_t level, int32_t *dist,
-                                         int32_t *parent, unsigned long long &nfound,
-                                         unsigned long long &dfound, unsigned long long &nexam) {
+                                         const uint32_t *front, int64_t sr, int32_t level, int32_t *dist,
+                                         int32_t *parent, BuCount &C) {
   const int lane = lane_id();
   const bool act = (unsigned)lane < cnt;
-  const unsigned slot = (head + lane) % kRing;
-  int32_t v = 0, deg = 0, k = 0;
+  const unsigned slot = (head + lane) & (kDefer - 1);
+  int32_t v = 0, deg = 0;
   int64_t row0 = 0;
   if (act) {
-    v = W.v[slot];
-    deg = W.deg[slot];
-    k = W.word[slot];
+    v = W.dv[slot];
+    deg = W.ddeg[slot];
     row0 = (int64_t)G.rp[v];
   }
   const bool heavy = act && deg > G.tbu;
@@ -669,15 +747,15 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
     const int64_t end = row0 + deg;
     for (int64_t j0 = row0 + 3; j0 < end; j0 += kBuUnroll) {
       int32_t x[kBuUnroll];
-      uint64_t f[kBuUnroll];
+      uint32_t f[kBuUnroll];
 #pragma unroll
       for (int q = 0; q < kBuUnroll; ++q) x[q] = (j0 + q < end) ? G.col[j0 + q] : -1;
 #pragma unroll
-      for (int q = 0; q < kBuUnroll; ++q) f[q] = (x[q] >= 0) ? front[x[q] >> 6] : 0ull;
+      for (int q = 0; q < kBuUnroll; ++q) f[q] = (x[q] >= 0) ? front[x[q] >> 5] : 0u;
       int first = -1;
 #pragma unroll
       for (int q = kBuUnroll - 1; q >= 0; --q)
-        if (x[q] >= 0 && ((f[q] >> (x[q] & 63)) & 1ull)) first = q;
+        if (x[q] >= 0 && ((f[q] >> (x[q] & 31)) & 1u)) first = q;
       if (first >= 0) {
         found = true;
 #pragma unroll
@@ -702,7 +780,7 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
       bool h = false;
       if (j < e0) {
         x = G.col[j];
-        h = (front[x >> 6] >> (x & 63)) & 1ull;
+        h = front_bit(front, x);
       }
       const uint64_t hb = __ballot(h);
       if (hb) {
@@ -720,30 +798,84 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
       }
     }
   }
-  if (act) nexam += (unsigned long long)ex;
+  if (act) C.exam += (unsigned long long)ex;
   if (found) {
     dist[v] = level + 1;
     if (parent) parent[v] = hit;
-    nfound += 1;
-    dfound += (unsigned long long)deg;
-    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[k]), 1ull << (v & 63));
+    C.found += 1;
+    C.fdeg += (unsigned long long)deg;
+    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[(v >> 6) - sr]), 1ull << (v & 63));
   }
-  (void)sr;
+}
+
+// Resolves one batch of `cnt` candidates (lane < cnt holds vertex v with
+// head record h): tests the head neighbours, records the finds, defers the
+// rest of the longer rows (draining 64 deferred rows when that many wait,
+// and every deferred row after the `last` batch of a run).
+template <class RowT>
+__device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, int32_t v, const int4 h, int cnt,
+                                           const uint32_t *front, int64_t sr, int32_t level, int32_t *dist,
+                                           int32_t *parent, unsigned &dh, unsigned &dc, bool last, BuCount &C) {
+  const int lane = lane_id();
+  const bool act = lane < cnt;
+  // the second and third head neighbours are tested only where the first
+  // misses (with hub-first rows most finds are at the first, and the
+  // frontier-bit gathers are the level's largest request count)
+  uint32_t f0 = 0, f1 = 0, f2 = 0;
+  if (act) f0 = front[h.y >> 5];  // degree >= 1: the first neighbour exists
+  if (act && !((f0 >> (h.y & 31)) & 1u)) {
+    if (h.z >= 0) f1 = front[h.z >> 5];
+    if (h.w >= 0) f2 = front[h.w >> 5];
+  }
+  bool found = false, defer = false;
+  int32_t hit = -1;
+  if (act) {
+    int32_t ex = h.x;
+    if ((f0 >> (h.y & 31)) & 1u) {
+      found = true; hit = h.y; ex = 1;
+    } else if (h.z >= 0 && ((f1 >> (h.z & 31)) & 1u)) {
+      found = true; hit = h.z; ex = 2;
+    } else if (h.w >= 0 && ((f2 >> (h.w & 31)) & 1u)) {
+      found = true; hit = h.w; ex = 3;
+    } else if (h.x > 3) {
+      defer = true;  // counted when its row is scanned
+    }
+    if (!defer) C.exam += (unsigned long long)ex;
+    C.scan += 1;
+  }
+  if (found) {
+    dist[v] = level + 1;
+    if (parent) parent[v] = hit;
+    C.found += 1;
+    C.fdeg += (unsigned long long)h.x;
+    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[(v >> 6) - sr]), 1ull << (v & 63));
+  }
+  const uint64_t dm = __ballot(defer);
+  if (defer) {
+    const unsigned slot = (dh + dc + lanes_below(dm)) & (kDefer - 1);
+    W.dv[slot] = v;
+    W.ddeg[slot] = h.x;
+  }
+  dc += (unsigned)__popcll(dm);
+  while (dc >= kWave || (last && dc > 0)) {  // uniform; the last batch may leave up to 127
+    const unsigned n = dc < kWave ? dc : kWave;
+    bu_drain(G, W, dh, n, front, sr, level, dist, parent, C);
+    dh = (dh + n) & (kDefer - 1);
+    dc -= n;
+  }
 }
 
 template <class RowT>
-__global__ void k_bu(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->dir != kBU) return;
-  extern __shared__ __align__(16) char lds[];
+__device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char *lds,
+                                         unsigned long long (&counts)[kPartials]) {
   BuWaveLds &W = reinterpret_cast<BuWaveLds *>(lds)[threadIdx.x >> 6];
-  const uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
+  const uint32_t *front = reinterpret_cast<const uint32_t *>(c->bcur ? G.bm[1] : G.bm[0]);
   uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
   const int32_t level = c->level;
   int32_t *dist = c->dist;
   int32_t *parent = c->parent;
   const int lane = lane_id();
-  unsigned long long nfound = 0, dfound = 0, nscan = 0, nexam = 0;
+  BuCount C;
   const int64_t wpb = blockDim.x >> 6;
   const int64_t nw = (int64_t)gridDim.x * wpb;
   const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
@@ -753,79 +885,38 @@ __global__ void k_bu(DevG<RowT> G) {
     const int nwd = (int)min((int64_t)kWave, w_end - sr);
     const uint64_t my_vis = lane < nwd ? G.vis[sr + lane] : ~0ull;
     W.mask[lane] = 0;
-    unsigned rhead = 0, rcount = 0;  // deferred ring (wave-uniform)
-    // Three-stage software pipeline over the run's words: while word k is
-    // resolved, the frontier words of word k+1's head neighbours and the
-    // head records of word k+2 are already in flight.
-    auto load_head = [&](int k) {
-      const uint64_t vwk = __shfl(my_vis, k);
-      return (vwk != ~0ull && !((vwk >> lane) & 1ull)) ? G.head[(sr + k) * kWave + lane]
-                                                      : make_int4(0, -1, -1, -1);
-    };
-    uint64_t fa0 = 0, fa1 = 0, fa2 = 0;
-    auto load_front = [&](const int4 &hh) {
-      fa0 = hh.y >= 0 ? front[hh.y >> 6] : 0ull;
-      fa1 = hh.z >= 0 ? front[hh.z >> 6] : 0ull;
-      fa2 = hh.w >= 0 ? front[hh.w >> 6] : 0ull;
-    };
-    int4 ha = load_head(0);
-    load_front(ha);
-    int4 hb = nwd > 1 ? load_head(1) : make_int4(0, -1, -1, -1);
-    // k == nwd is an extra pass that only drains what is left in the ring
-    for (int k = 0; k <= nwd; ++k) {
-      if (k < nwd) {
-        const uint64_t vw = __shfl(my_vis, k);
-        const int4 h = ha;
-        const uint64_t f0 = fa0, f1 = fa1, f2 = fa2;
-        if (k + 1 < nwd) {
-          load_front(hb);
-          ha = hb;
-        }
-        if (k + 2 < nwd) hb = load_head(k + 2);
-        if (vw != ~0ull) {
-          const int64_t v = (sr + k) * kWave + lane;  // ids >= n are marked visited in vw
-          const bool unvisited = !((vw >> lane) & 1ull);
-          bool found = false, defer = false;
-          int32_t hit = -1;
-          if (unvisited) {
-            const int32_t x0 = h.y, x1 = h.z, x2 = h.w;
-            int64_t ex = h.x;
-            if (x0 >= 0 && ((f0 >> (x0 & 63)) & 1ull)) {
-              found = true; hit = x0; ex = 1;
-            } else if (x1 >= 0 && ((f1 >> (x1 & 63)) & 1ull)) {
-              found = true; hit = x1; ex = 2;
-            } else if (x2 >= 0 && ((f2 >> (x2 & 63)) & 1ull)) {
-              found = true; hit = x2; ex = 3;
-            } else if (h.x > 3) {
-              defer = true;  // counted when its row is scanned
-            }
-            if (!defer) nexam += (unsigned long long)ex;
-            nscan += 1;
-            if (found) {
-              dist[v] = level + 1;
-              if (parent) parent[v] = hit;
-              nfound += 1;
-              dfound += (unsigned long long)h.x;
-            }
-          }
-          const uint64_t fm = __ballot(found);
-          if (lane == 0 && fm) W.mask[k] = fm;
-          const uint64_t dm = __ballot(defer);
-          if (defer) {
-            const unsigned slot = (rhead + rcount + lanes_below(dm)) % kRing;
-            W.v[slot] = (int32_t)v;
-            W.deg[slot] = h.x;
-            W.word[slot] = (uint8_t)k;
-          }
-          rcount += (unsigned)__popcll(dm);
-        }
+    uint64_t act = __ballot(my_vis != ~0ull);  // words with an unvisited vertex
+    unsigned ch = 0, ct = 0;                   // candidate ring head / tail (uniform)
+    unsigned dh = 0, dc = 0;                   // deferred ring head / count
+    int pc = 0;                                // candidates of the batch in flight
+    int32_t pv = 0;
+    int4 ph = make_int4(0, 0, -1, -1);
+    for (;;) {
+      if (act) {
+        const int k = __builtin_ctzll(act);
+        act &= act - 1;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)my_vis, k);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(my_vis >> 32), k);
+        const uint64_t un = ~(((uint64_t)hi << 32) | lo);  // its unvisited vertices
+        if ((un >> lane) & 1ull) W.cand[(ct + lanes_below(un)) & (kCand - 1)] = (int32_t)((sr + k) * kWave + lane);
+        ct += (unsigned)__popcll(un);
+        if (ct - ch < (unsigned)kWave && act) continue;  // uniform
       }
-      if (rcount >= kWave || (k == nwd && rcount > 0)) {  // uniform
-        const unsigned cnt = rcount < kWave ? rcount : kWave;
-        bu_drain(G, W, rhead, cnt, front, sr, level, dist, parent, nfound, dfound, nexam);
-        rhead = (rhead + cnt) % kRing;
-        rcount -= cnt;
+      // next batch: load its head records, then resolve the one in flight
+      // (an empty next batch marks the run's last resolve)
+      const int cnt = (int)min(ct - ch, (unsigned)kWave);
+      if (cnt == 0 && pc == 0) break;
+      int32_t bv = 0;
+      int4 bh = make_int4(0, 0, -1, -1);
+      if (lane < cnt) {
+        bv = W.cand[(ch + lane) & (kCand - 1)];
+        bh = G.head[bv];
       }
+      ch += cnt;
+      if (pc) bu_resolve(G, W, pv, ph, pc, front, sr, level, dist, parent, dh, dc, cnt == 0, C);
+      pv = bv;
+      ph = bh;
+      pc = cnt;
     }
     // one coalesced store of the run's next-frontier and visited words
     if (lane < nwd) {
@@ -834,75 +925,102 @@ __global__ void k_bu(DevG<RowT> G) {
       if (m) G.vis[sr + lane] = my_vis | m;
     }
   }
-  block_partials<4>(G, {nfound, dfound, nscan, nexam});
+  counts[0] = C.found;
+  counts[1] = C.fdeg;
+  counts[2] = C.scan;
+  counts[3] = C.exam;
 }
 
-// Separate decide step: one workgroup after the level's kernels.
-__global__ void __launch_bounds__(1024) k_decide(Ctl *c, LevelRec *recs, unsigned long long *partials) {
-  unsigned long long tot[kPartials];
-  reduce_partials<false>(partials, kMaxBlocks, tot);
-  if (threadIdx.x != 0 || c->done) return;
-  decide_apply(c, recs, tot);
-}
+// One level, in the direction the decide step chose: top-down roles over
+// the grid (workgroups [0, nb_small) thread per vertex, the next nb_med
+// wavefront per vertex, the rest one workgroup per edge chunk) or bottom-up
+// word runs over the whole grid.  D is the direction when the launcher
+// knows it (host loop: separate top-down and bottom-up instances), or
+// kAnyDir to read it from the control block (captured loop).
+constexpr int kAnyDir = 2;
 
-// Queue -> bitmap: set the bit of every frontier vertex in the current
-// frontier bitmap (kept all-zero while levels run top-down).
-template <class RowT>
-__global__ void k_conv_q2b(DevG<RowT> G) {
+template <class RowT, int D>
+__global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t mode) {
   const Ctl *c = G.ctl;
-  if (c->done || c->conv != kConvQ2B) return;
+  if (c->done || (D != kAnyDir && c->dir != D)) return;
+  extern __shared__ __align__(16) char lds[];
+  unsigned long long counts[kPartials] = {0, 0, 0, 0};
+  if (D == kTD || (D == kAnyDir && c->dir == kTD)) {
+    const Stage S = stage_open(lds);
+    unsigned long long tc[2];
+    td_level(G, td_level_state(c), S, blockIdx.x, gridDim.x, nb_small, nb_med, tc);
+    counts[0] = tc[0];
+    counts[1] = tc[1];
+  } else {
+    bu_level(G, c, lds, counts);
+  }
+  end_level<kPartials>(G, mode, counts);
+}
+
+// Frontier conversion before a level whose direction differs from the one
+// before it (one kernel serves both directions of change):
+//   queue -> bitmap: the bit of every frontier vertex is set in the current
+//     frontier bitmap (kept all-zero while levels run top-down);
+//   bitmap -> queue: the frontier bitmap is compacted into degree-bucketed
+//     queues and cleared on the way (so it is all-zero again for the next
+//     queue -> bitmap conversion).  A wavefront loads 64 words with one
+//     coalesced load and visits only the nonzero ones.
+template <class RowT>
+__global__ void k_conv(DevG<RowT> G) {
+  const Ctl *c = G.ctl;
+  const int32_t conv = c->conv;
+  if (c->done || conv == kConvNone) return;
   const int q = c->qcur;
   uint64_t *bm = c->bcur ? G.bm[1] : G.bm[0];
-  const int64_t c0 = c->qcnt[q][kSmall], c1 = c->qcnt[q][kMedium], c2 = c->qcnt[q][kLarge];
-  const int32_t *qs = q ? G.qs[1] : G.qs[0];
-  const int32_t *qm = q ? G.qm[1] : G.qm[0];
-  const uint64_t *ql = q ? G.ql[1] : G.ql[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c0 + c1 + c2; i += stride) {
-    int32_t v;
-    if (i < c0) {
-      v = qs[i];
-    } else if (i < c0 + c1) {
-      v = qm[i - c0];
-    } else {
-      const uint64_t e = ql[i - c0 - c1];
-      if (e >> 32) continue;  // chunk > 0 of a vertex already counted
-      v = (int32_t)(uint32_t)e;
+  if (conv == kConvQ2B) {
+    const int64_t c0 = c->qcnt[q][kSmall], c1 = c->qcnt[q][kMedium], c2 = c->qcnt[q][kLarge];
+    const int32_t *qs = q ? G.qs[1] : G.qs[0];
+    const int32_t *qm = q ? G.qm[1] : G.qm[0];
+    const uint64_t *ql = q ? G.ql[1] : G.ql[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c0 + c1 + c2; i += stride) {
+      int32_t v;
+      if (i < c0) {
+        v = qs[i];
+      } else if (i < c0 + c1) {
+        v = qm[i - c0];
+      } else {
+        const uint64_t e = ql[i - c0 - c1];
+        if (e >> 32) continue;  // chunk > 0 of a vertex already counted
+        v = (int32_t)(uint32_t)e;
+      }
+      atomicOr(reinterpret_cast<unsigned long long *>(bm + (v >> 6)), 1ull << (v & 63));
     }
-    atomicOr(reinterpret_cast<unsigned long long *>(bm + (v >> 6)), 1ull << (v & 63));
+    return;
   }
-}
-
-// Bitmap -> queue: compact the frontier bitmap into degree-bucketed queues,
-// clearing each word read (so the bitmap is all-zero again for the next
-// queue -> bitmap conversion).
-template <class RowT>
-__global__ void k_conv_b2q(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  if (c->done || c->conv != kConvB2Q) return;
   extern __shared__ __align__(16) char lds[];
   const Stage S = stage_open(lds);
-  const int qn = c->qcur;
-  uint64_t *front = c->bcur ? G.bm[1] : G.bm[0];
   const int lane = lane_id();
   const int64_t wpb = blockDim.x >> 6;
   const int64_t nw = (int64_t)gridDim.x * wpb;
   const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
   const int64_t per = (G.words + nw - 1) / nw;
-  const int64_t w1 = min(G.words, (gw + 1) * per);
-  for (int64_t k = 0; k < per; ++k) {  // workgroup-uniform rounds
-    const int64_t w = gw * per + k;
-    const uint64_t word = w < w1 ? front[w] : 0ull;
-    if (word) {  // uniform within the wavefront
-      if (lane == 0) front[w] = 0;
-      const int64_t v = w * kWave + lane;
-      const bool in = (word >> lane) & 1ull;
+  const int64_t w0 = gw * per;
+  const int64_t w1 = min(G.words, w0 + per);
+  for (int64_t r = 0; r < per; r += kWave) {  // workgroup-uniform rounds of 64 words
+    const int64_t sr = w0 + r;
+    const uint64_t word = sr + lane < w1 ? bm[sr + lane] : 0ull;
+    if (word) bm[sr + lane] = 0;
+    uint64_t nz = __ballot(word != 0ull);
+    while (nz) {
+      const int k = __builtin_ctzll(nz);
+      nz &= nz - 1;
+      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)word, k);
+      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(word >> 32), k);
+      const uint64_t wk = ((uint64_t)hi << 32) | lo;
+      const int64_t v = (sr + k) * kWave + lane;
+      const bool in = (wk >> lane) & 1ull;
       const int64_t deg = in ? (int64_t)G.head[v].x : 0;
-      wave_stage(G, S, qn, in, (int32_t)v, deg);
+      wave_stage(G, S, q, in, (int32_t)v, deg);
     }
-    stage_flush(G, S, qn, true);
+    stage_flush(G, S, q, true);
   }
-  stage_flush(G, S, qn);
+  stage_flush(G, S, q);
 }
 
 // Head records: degree and the first three neighbours (-1 where the row is
@@ -955,8 +1073,11 @@ DevG<RowT> make_devg(bfs_graph *g) {
 struct Shapes {
   int bs;            // threads per workgroup
   int wpb;           // wavefronts per workgroup
-  int words_blocks;  // grid of the word-parallel kernels (bottom-up, bitmap -> queue)
+  int words_blocks;  // grid of the bitmap -> queue conversion
+  int bu_blocks;     // grid of the bottom-up kernel
   size_t lds;        // dynamic LDS of the staging kernels
+  size_t level_lds;  // dynamic LDS of the level kernel
+  int conv_blocks;   // grid of the conversion kernel
 };
 
 Shapes shapes_of(const bfs_graph *g) {
@@ -964,7 +1085,10 @@ Shapes shapes_of(const bfs_graph *g) {
   s.bs = g->params.block_size;
   s.wpb = s.bs / kWave;
   s.words_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
+  s.bu_blocks = g->params.bu_blocks > 0 ? g->params.bu_blocks : s.words_blocks;
   s.lds = stage_bytes(s.bs);
+  s.level_lds = std::max(s.lds, bu_lds_bytes(s.bs));
+  s.conv_blocks = std::min(s.words_blocks, 128);
   return s;
 }
 
@@ -983,20 +1107,31 @@ TdRoles td_roles(const Shapes &S, int64_t c0, int64_t c1, int64_t c2) {
 }
 
 template <class RowT>
-void launch_td(const DevG<RowT> &G, const Shapes &S, const TdRoles &r, hipStream_t st, int fused_decide = 0) {
-  hipLaunchKernelGGL(k_td<RowT>, dim3(r.small + r.med + r.large), dim3(S.bs), S.lds, st, G, r.small, r.med,
-                     fused_decide);
+void launch_level(const DevG<RowT> &G, const Shapes &S, int dir, int blocks, const TdRoles &r, hipStream_t st) {
+  auto *k = dir == kTD ? k_level<RowT, kTD> : dir == kBU ? k_level<RowT, kBU> : k_level<RowT, kAnyDir>;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(S.bs), S.level_lds, st, G, r.small, r.med, (int32_t)kFusedDecide);
 }
 
-template <class RowT>
-void launch_level_tail(bfs_graph *g, hipStream_t st) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, st, g->ctl, g->recs, g->partials);
-}
-
-int read_ctl(bfs_graph *g, hipStream_t st) {
-  BFS_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-  BFS_HIP(hipStreamSynchronize(st));
-  return BFS_OK;
+// Waits for publication number `seq` of a device-driven run (its last
+// level).  Sets *published to false when the stream drained without it (the
+// captured chunk ended before the search did).
+int wait_final(bfs_graph *g, hipStream_t st, uint32_t seq, bool *published) {
+  volatile uint32_t *p = &g->ctl_host->seq;
+  for (uint64_t spin = 0;; ++spin) {
+    if (__atomic_load_n(p, __ATOMIC_ACQUIRE) == seq) {
+      *published = true;
+      return BFS_OK;
+    }
+    if ((spin & 255) == 255) {
+      const hipError_t q = hipStreamQuery(st);
+      if (q != hipSuccess && q != hipErrorNotReady)
+        return fail(BFS_ERR_DEVICE, "level kernels failed: %s", hipGetErrorString(q));
+      if (q == hipSuccess) {
+        *published = __atomic_load_n(p, __ATOMIC_ACQUIRE) == seq;
+        return BFS_OK;
+      }
+    }
+  }
 }
 
 // Waits until the device has published level state number `seq` in the
@@ -1054,12 +1189,8 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       return rc;
     }
     if (h.done) break;
-    if (h.conv == kConvQ2B) {
-      const int64_t qtotal = (int64_t)h.qcnt[h.qcur][0] + h.qcnt[h.qcur][1] + h.qcnt[h.qcur][2];
-      hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(qtotal, S.bs, 4096)), dim3(S.bs), 0, st, G);
-    } else if (h.conv == kConvB2Q) {
-      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, st, G);
-    }
+    if (h.conv != kConvNone)
+      hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, st, G);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing) {  // the events bracket the level's direction kernel only
       e0 = level_event(g, nev++);
@@ -1073,16 +1204,19 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
         c0 = c1 = h.n_f;
         c2 = g->max_degree > G.t2 ? h.m_f / G.t2 + h.n_f : 0;
       }
-      launch_td(G, S, td_roles(S, c0, c1, c2), st);
+      const TdRoles r = td_roles(S, c0, c1, c2);
+      launch_level(G, S, kTD, r.small + r.med + r.large, r, st);
     } else {
-      hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), bu_lds_bytes(S.bs), st, G);
+      launch_level(G, S, kBU, S.bu_blocks, TdRoles{0, 0, 0}, st);
     }
     if (timing) BFS_HIP(hipEventRecord(e1, st));
-    launch_level_tail<RowT>(g, st);
     BFS_HIP(hipGetLastError());
   }
   if (timing) {
+    // the last level published `done` from inside its kernel, which may
+    // still be finishing
     level_ms.clear();
+    if (nev > 0) BFS_HIP(hipEventSynchronize(g->level_events[nev - 1]));
     for (size_t i = 0; i + 1 < nev; i += 2) {
       float ms = 0.f;
       BFS_HIP(hipEventElapsedTime(&ms, g->level_events[i], g->level_events[i + 1]));
@@ -1106,17 +1240,14 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
   r.small = blocks_for(g->n, S.bs, gb);
   r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, std::max(1, gb / 2)) : 0;
   r.large = g->max_degree > G.t2 ? std::max(1, gb / 2) : 0;
-  const int fused = hybrid ? 0 : 1;  // top-down only: the last workgroup decides
+  // a hybrid level is [conversion, level]; the level kernel's grid serves
+  // both directions (extra workgroups join the per-chunk top-down role)
+  const int blocks = hybrid ? std::max(r.small + r.med + r.large, S.bu_blocks) : r.small + r.med + r.large;
   release_graph_exec(g);
   BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int l = 0; l < K; ++l) {
-    if (hybrid) {
-      hipLaunchKernelGGL(k_conv_q2b<RowT>, dim3(blocks_for(g->n, S.bs, 4096)), dim3(S.bs), 0, cs, G);
-      hipLaunchKernelGGL(k_conv_b2q<RowT>, dim3(S.words_blocks), dim3(S.bs), S.lds, cs, G);
-    }
-    launch_td(G, S, r, cs, fused);
-    if (hybrid) hipLaunchKernelGGL(k_bu<RowT>, dim3(S.words_blocks), dim3(S.bs), bu_lds_bytes(S.bs), cs, G);
-    if (!fused) launch_level_tail<RowT>(g, cs);
+    if (hybrid) hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, cs, G);
+    launch_level(G, S, kAnyDir, blocks, r, cs);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
@@ -1134,10 +1265,14 @@ int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
   if (!g->gexec || g->gexec_levels != K) {
     if ((rc = capture_levels(g, G, policy, K))) return rc;
   }
+  // the init kernel published number pub_seq + 1, the last level publishes
+  // pub_seq + 2; replay the chunk until it has
+  const uint32_t target = g->pub_seq + 2;
   for (;;) {
     BFS_HIP(hipGraphLaunch(g->gexec, st));
-    if ((rc = read_ctl(g, st))) return rc;
-    if (g->ctl_host->done) break;
+    bool published = false;
+    if ((rc = wait_final(g, st, target, &published))) return rc;
+    if (published) break;
   }
   return BFS_OK;
 }
@@ -1164,7 +1299,11 @@ int persistent_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st) {
   void *args[] = {const_cast<DevG<RowT> *>(&G), &a_small, &a_med};
   BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_td_persistent<RowT>), dim3(blocks),
                                      dim3(S.bs), args, S.lds, st));
-  return read_ctl(g, st);
+  bool published = false;
+  int rc = wait_final(g, st, g->pub_seq + 2, &published);
+  if (rc) return rc;
+  if (!published) return fail(BFS_ERR_DEVICE, "the persistent search ended without publishing its result");
+  return BFS_OK;
 }
 
 template <class RowT>
@@ -1181,7 +1320,8 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   BFS_HIP(hipEventRecord(g->ev_start, st));
   hipLaunchKernelGGL(k_init<RowT>, dim3(blocks_for(std::max(g->n, g->words), bs, 4096)), dim3(bs), 0, st,
                      G, s, dist, parent, (int32_t)policy, g->params.alpha, g->params.beta, g->nnz,
-                     g->rec_cap, loop == BFS_LOOP_HOST ? g->ctl_host_dev : nullptr, g->pub_seq);
+                     g->rec_cap, g->ctl_host_dev, g->pub_seq,
+                     (int32_t)(loop == BFS_LOOP_HOST ? kPubEvery : kPubFinal));
   BFS_HIP(hipGetLastError());
   std::vector<float> level_ms;
   int rc = loop == BFS_LOOP_HOST    ? host_loop(g, G, st, level_ms)

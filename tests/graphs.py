@@ -137,3 +137,27 @@ CLOSED_FORMS = {
     "binary_tree": lambda: binary_tree(100),
     "two_paths": lambda: two_paths(15, 9),
 }
+
+
+def deferred_rows(n=8192, nf=1000, seed=3):
+    """Source 0 joined to the nf highest ids F; every other vertex gets one
+    random neighbour in F (its largest id, so last in its sorted row) and
+    0-4 random neighbours below F, so most rows have three non-frontier
+    neighbours ahead of the frontier one.  Distances: 1 on F, 2 elsewhere."""
+    rng = np.random.default_rng(seed)
+    lo = n - nf
+    us, vs = [np.zeros(nf, np.int64)], [np.arange(lo, n)]
+    others = np.arange(1, lo)
+    us.append(others); vs.append(rng.integers(lo, n, len(others)))
+    k = rng.integers(0, 5, len(others))
+    src = np.repeat(others, k)
+    us.append(src); vs.append(rng.integers(1, lo, len(src)))
+    u, v = np.concatenate(us), np.concatenate(vs)
+    keep = u != v
+    g = graphgen.from_edges(n, u[keep], v[keep], f"deferred{n}")
+
+    def f(s):
+        assert s == 0
+        d = np.full(n, 2, np.int64); d[lo:] = 1; d[0] = 0
+        return d
+    return g, f

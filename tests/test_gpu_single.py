@@ -249,3 +249,49 @@ def test_persistent_loop_grid_sizes(bfs, rmat16, blocks):
         for s in graphgen.sources(rmat16, 2, seed=5):
             check_single(rmat16, gh, s)
     gh.close()
+
+
+@pytest.mark.parametrize("bs,bu_blocks", [(64, 1), (64, 3), (128, 2), (512, 0)])
+def test_bu_runs_of_many_words(bs, bu_blocks):
+    """Bottom-up grids far smaller than the word count, so each wavefront
+    takes several 64-word runs of many 64-candidate batches: deferred rows
+    pile up to the ring's limit and the last batch of a run leaves more
+    than 64 of them to scan."""
+    bfs = library()
+    say("bottom-up runs: block", bs, "bu_blocks", bu_blocks)
+    g, f = graphs.deferred_rows()
+    gh = upload(g)
+    bfs.bfs_set_params(gh, policy=2, block_size=bs, bu_blocks=bu_blocks)
+    _, _, run, levels = check_single(g, gh, 0, ref=f(0).astype(np.int32))
+    assert levels[1]["direction"] == 1 and levels[1]["examined"] > 4 * levels[1]["scanned"] // 2
+    gh.close()
+
+
+@pytest.mark.parametrize("bu_blocks", [1, 5, 64])
+@pytest.mark.parametrize("sort", [False, True])
+def test_rmat16_bu_blocks(rmat16, bu_blocks, sort):
+    bfs = library()
+    g = rmat16
+    say("rmat16 bu_blocks", bu_blocks, "sorted", sort)
+    gh = upload(g, bfs.BFS_SORT_NEIGHBORS if sort else 0)
+    bfs.bfs_set_params(gh, block_size=64, bu_blocks=bu_blocks)
+    order = hub_first(g) if sort else None
+    for pol in (1, 2):
+        bfs.bfs_set_params(gh, policy=pol)
+        for s in graphgen.sources(g, 3, seed=19):
+            check_single(g, gh, s, scan_order=order)
+    gh.close()
+
+
+@pytest.mark.parametrize("policy", [1, 3])
+def test_level_timing(rmat16, policy):
+    """collect_timing: every level of a host-loop run gets a device time."""
+    bfs = library()
+    g = rmat16
+    say("rmat16 level timing, policy", policy)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, policy=policy, loop=1, collect_timing=1)
+    for s in graphgen.sources(g, 4, seed=29):
+        _, _, run, levels = check_single(g, gh, s)
+        assert run["loop"] == 1 and all(lv["ms"] > 0 for lv in levels), levels
+    gh.close()
