@@ -72,14 +72,18 @@ typedef enum bfs_policy {
 
 /* Level-loop drivers (bfs_params.loop). */
 typedef enum bfs_loop {
-  BFS_LOOP_AUTO = 0,  /* GRAPH for top-down-only runs, HOST otherwise */
+  BFS_LOOP_AUTO = 0,  /* GRAPH */
   BFS_LOOP_HOST = 1,  /* host issues each level and reads the level counters back */
   BFS_LOOP_GRAPH = 2, /* replay a captured hipGraph of `graph_chunk_levels` levels
                          whose kernels test device-side direction / done flags */
-  BFS_LOOP_PERSISTENT = 3 /* top-down-only runs: one cooperative launch of
-                             `graph_td_blocks` workgroups runs every level,
-                             levels separated by a grid barrier (hybrid
-                             policies fall back to HOST) */
+  BFS_LOOP_PERSISTENT = 3, /* top-down-only runs: one cooperative launch of
+                              `graph_td_blocks` workgroups runs every level,
+                              levels separated by a grid barrier (hybrid
+                              policies fall back to HOST) */
+  BFS_LOOP_QUEUED = 4 /* the host keeps `queue_ahead` levels enqueued beyond the
+                         last one the device has published; each level kernel
+                         reads its direction on the device, so the device never
+                         waits for the host between levels */
 } bfs_loop;
 
 /* Tunables.  bfs_default_params() fills defaults; zero fields passed to
@@ -95,8 +99,8 @@ typedef struct bfs_params {
                                  scanned by the whole wavefront (default 2048) */
   int32_t block_size;         /* threads per workgroup of the level kernels (default 512) */
   int32_t loop;               /* bfs_loop */
-  int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 32) */
-  int32_t collect_timing;     /* nonzero: time each level with HIP events (HOST loop) */
+  int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 8) */
+  int32_t collect_timing;     /* nonzero: time each level with HIP events (HOST and QUEUED loops) */
   int32_t msbfs_block_size;   /* batched search: threads per workgroup (default 256) */
   int32_t msbfs_bu_percent;   /* batched search: a level runs bottom-up when its frontier
                                  edge count exceeds this percent of nnz (default 5) */
@@ -105,7 +109,9 @@ typedef struct bfs_params {
   int32_t bu_blocks;          /* bottom-up: workgroups of the grid, each wavefront taking an equal
                                  share of the visited words (0 = automatic: one word per
                                  wavefront up to 1024 workgroups; at most 1024) */
-  int32_t reserved[2];
+  int32_t queue_ahead;        /* QUEUED loop: levels kept enqueued ahead of the device (default 2,
+                                 at most 64) */
+  int32_t reserved[1];
 } bfs_params;
 
 /* One record per executed level of the last bfs_run on a graph. */

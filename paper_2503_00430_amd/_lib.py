@@ -28,6 +28,7 @@ BFS_LOOP_AUTO = 0
 BFS_LOOP_HOST = 1
 BFS_LOOP_GRAPH = 2
 BFS_LOOP_PERSISTENT = 3
+BFS_LOOP_QUEUED = 4
 
 BFS_REQ_QUEUED = 0
 BFS_REQ_RUNNING = 1
@@ -42,7 +43,7 @@ class bfs_params(ctypes.Structure):
     _fields_ = [(name, _i32) for name in (
         "policy", "alpha", "beta", "td_wave_degree", "td_block_degree", "bu_wave_degree",
         "block_size", "loop", "graph_chunk_levels", "collect_timing", "msbfs_block_size",
-        "msbfs_bu_percent", "graph_td_blocks", "bu_blocks")] + [("reserved", _i32 * 2)]
+        "msbfs_bu_percent", "graph_td_blocks", "bu_blocks", "queue_ahead")] + [("reserved", _i32 * 1)]
 
 
 class bfs_level_stats(ctypes.Structure):

@@ -145,11 +145,12 @@ static bfs_params default_params() {
   p.bu_wave_degree = 2048;
   p.block_size = 512;
   p.loop = BFS_LOOP_AUTO;
-  p.graph_chunk_levels = 32;
+  p.graph_chunk_levels = 8;
   p.collect_timing = 0;
   p.msbfs_block_size = 256;
   p.msbfs_bu_percent = 5;
   p.graph_td_blocks = 128;
+  p.queue_ahead = 2;
   return p;
 }
 
@@ -164,12 +165,14 @@ static int check_params(const bfs_params &p) {
   for (int bs : {p.block_size, p.msbfs_block_size})
     if (bs < 64 || bs > 1024 || bs % 64)
       return fail(BFS_ERR_INVALID_ARG, "block sizes must be multiples of 64 in [64, 1024]");
-  if (p.loop < BFS_LOOP_AUTO || p.loop > BFS_LOOP_PERSISTENT)
+  if (p.loop < BFS_LOOP_AUTO || p.loop > BFS_LOOP_QUEUED)
     return fail(BFS_ERR_INVALID_ARG, "unknown loop driver %d", p.loop);
   if (p.graph_chunk_levels < 1 || p.graph_chunk_levels > 4096)
     return fail(BFS_ERR_INVALID_ARG, "graph_chunk_levels must be in [1, 4096]");
   if (p.graph_td_blocks < 1 || p.graph_td_blocks > 512)
     return fail(BFS_ERR_INVALID_ARG, "graph_td_blocks must be in [1, 512]");
+  if (p.queue_ahead < 1 || p.queue_ahead > 64)
+    return fail(BFS_ERR_INVALID_ARG, "queue_ahead must be in [1, 64]");
   if (p.bu_blocks < 0 || p.bu_blocks > kMaxBlocks)
     return fail(BFS_ERR_INVALID_ARG, "bu_blocks must be in [0, %d]", kMaxBlocks);
   if (p.msbfs_bu_percent < 0 || p.msbfs_bu_percent > 100)
@@ -366,6 +369,7 @@ int bfs_set_params(bfs_graph_t g, const bfs_params *p) {
   if (q.f == 0) q.f = d.f
   DEF(alpha); DEF(beta); DEF(td_wave_degree); DEF(td_block_degree); DEF(bu_wave_degree);
   DEF(block_size); DEF(graph_chunk_levels); DEF(msbfs_block_size); DEF(graph_td_blocks);
+  DEF(queue_ahead);
 #undef DEF
   int rc = check_params(q);
   if (rc) return rc;

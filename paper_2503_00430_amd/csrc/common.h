@@ -59,6 +59,8 @@ struct alignas(256) Ctl {
   uint32_t bar_gen;
   uint32_t seq;     // publications so far (the mirror's copy is written last)
   int32_t pub_mode; // kPubEvery: publish after every level; kPubFinal: only the last
+  uint32_t seq_wip; // the mirror's copy: number of the publication being written
+                    // (written first, so a reader can tell a torn copy)
 };
 
 // Level kernels run at most kMaxBlocks workgroups; each writes its counts

@@ -52,7 +52,8 @@ namespace {
 // slot of the partials array (plain stores; the decide step reduces them).
 // Every thread of the workgroup must call it.
 template <int K, class RowT>
-__device__ __forceinline__ void block_partials(const DevG<RowT> &G, const unsigned long long (&v)[K]) {
+__device__ __forceinline__ void block_partials(const DevG<RowT> &G, const unsigned long long (&v)[K],
+                                               unsigned slot = blockIdx.x) {
   __shared__ unsigned long long part[K][16];
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -65,7 +66,7 @@ __device__ __forceinline__ void block_partials(const DevG<RowT> &G, const unsign
     unsigned long long t = 0;
     const int nw = blockDim.x >> 6;
     for (int i = 0; i < nw; ++i) t += part[threadIdx.x][i];
-    G.partials[(size_t)blockIdx.x * kPartials + threadIdx.x] = t;
+    G.partials[(size_t)slot * kPartials + threadIdx.x] = t;
   }
 }
 
@@ -210,6 +211,8 @@ __device__ void publish(Ctl *c) {
   if (!m) return;
   const uint32_t seq = c->seq + 1;
   c->seq = seq;
+  __hip_atomic_store(&m->seq_wip, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
   const uint64_t *src = reinterpret_cast<const uint64_t *>(c);
   uint64_t *dst = reinterpret_cast<uint64_t *>(m);
   constexpr int kWords = (int)(offsetof(Ctl, seq) / sizeof(uint64_t));
@@ -563,28 +566,31 @@ enum LevelMode : int32_t {
 // the workgroup call it.
 constexpr int kFenceDecideBlocks = 64;
 
+// `rank` numbers the nactive workgroups that take part (workgroups with no
+// work in the level exit before and do not arrive).
 template <int K, class RowT>
-__device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, const unsigned long long (&v)[K]) {
+__device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, const unsigned long long (&v)[K],
+                                          unsigned rank, unsigned nactive) {
   if (!(mode & kFusedDecide)) {
-    block_partials<K>(G, v);
+    block_partials<K>(G, v, rank);
     return;
   }
   uint32_t *arrive = reinterpret_cast<uint32_t *>(G.partials + kArriveOffset);
   constexpr int kLineU32 = 2 * kLineU64;
-  if (gridDim.x <= (unsigned)kFenceDecideBlocks) {
-    block_partials<K>(G, v);  // written by wave 0, whose fence below releases them
+  if (nactive <= (unsigned)kFenceDecideBlocks) {
+    block_partials<K>(G, v, rank);  // written by wave 0, whose fence below releases them
     __shared__ int last;
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
-      last = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u) == gridDim.x - 1;
+      last = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u) == nactive - 1;
       if (last) atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
     }
     __syncthreads();
     if (last) {
       __threadfence();
       unsigned long long tot[kPartials];
-      reduce_partials<true>(G.partials, gridDim.x, tot);
+      reduce_partials<true>(G.partials, (int)nactive, tot);
       if (threadIdx.x == 0) decide_apply(G.ctl, G.recs, tot);
     }
     return;
@@ -597,34 +603,40 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
     if (lane_id() == 0) part[k][w] = sum;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  unsigned long long t[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    t[k] = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t[k] += part[k][i];
-  }
+  if (threadIdx.x >= kWave) return;  // wave 0 finishes; its lanes work in parallel
+  const int lane = threadIdx.x;
   unsigned long long *acc = G.partials + kAccOffset;
-  const unsigned nb = gridDim.x;
-  const unsigned grp = blockIdx.x % kArriveGroups;
-  const unsigned gsize = (nb - grp + kArriveGroups - 1) / kArriveGroups;
-  const unsigned ngroups = nb < (unsigned)kArriveGroups ? nb : (unsigned)kArriveGroups;
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (t[k]) atomicAdd(&acc[(grp * kPartials + k) * kLineU64], t[k]);
+  const unsigned grp = rank % kArriveGroups;
+  const unsigned gsize = (nactive - grp + kArriveGroups - 1) / kArriveGroups;
+  const unsigned ngroups = nactive < (unsigned)kArriveGroups ? nactive : (unsigned)kArriveGroups;
+  if (lane < K) {
+    unsigned long long t = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += part[lane][i];
+    if (t) atomicAdd(&acc[(grp * kPartials + lane) * kLineU64], t);
+  }
   // the adds must have completed before this workgroup is counted
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  if (atomicAdd(&arrive[grp * kLineU32], 1u) != gsize - 1) return;
-  atomicExch(&arrive[grp * kLineU32], 0u);
-  if (atomicAdd(&arrive[kArriveGroups * kLineU32], 1u) != ngroups - 1) return;
-  atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
+  unsigned arrived = 0;
+  if (lane == 0) arrived = atomicAdd(&arrive[grp * kLineU32], 1u);
+  if (__shfl(arrived, 0) != gsize - 1) return;
+  if (lane == 0) {
+    atomicExch(&arrive[grp * kLineU32], 0u);
+    arrived = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u);
+  }
+  if (__shfl(arrived, 0) != ngroups - 1) return;
+  if (lane == 0) atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
+  // lane g * kPartials + k takes accumulator k of group g; sums over the
+  // lanes of equal k (lane mod kPartials) give the totals
+  static_assert((kPartials & (kPartials - 1)) == 0 && kArriveGroups * kPartials <= kWave,
+                "the lane mapping needs a power-of-two kPartials and one lane per accumulator");
+  unsigned long long x = 0;
+  if ((unsigned)lane < ngroups * kPartials) x = atomicExch(&acc[(size_t)lane * kLineU64], 0ull);
+#pragma unroll
+  for (int o = kPartials; o < kWave; o <<= 1) x += __shfl_xor(x, o);
   unsigned long long tot[kPartials];
 #pragma unroll
-  for (int k = 0; k < kPartials; ++k) {
-    tot[k] = 0;
-    for (unsigned gi = 0; gi < ngroups; ++gi) tot[k] += atomicExch(&acc[(gi * kPartials + k) * kLineU64], 0ull);
-  }
-  decide_apply(G.ctl, G.recs, tot);
+  for (int k = 0; k < kPartials; ++k) tot[k] = __shfl(x, k);
+  if (lane == 0) decide_apply(G.ctl, G.recs, tot);
 }
 
 // Persistent top-down search (top-down-only policies): every level of the
@@ -945,16 +957,31 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
   if (c->done || (D != kAnyDir && c->dir != D)) return;
   extern __shared__ __align__(16) char lds[];
   unsigned long long counts[kPartials] = {0, 0, 0, 0};
+  unsigned rank = blockIdx.x, nactive = gridDim.x;
   if (D == kTD || (D == kAnyDir && c->dir == kTD)) {
+    // only the workgroups whose role has work this level take part
+    const TdLevel T = td_level_state(c);
+    const int64_t b = blockIdx.x;
+    const int64_t nb_large = (int64_t)gridDim.x - nb_small - nb_med;
+    const int64_t a_s = min((int64_t)nb_small, (T.cnt[kSmall] + blockDim.x - 1) / blockDim.x);
+    const int64_t a_m = min((int64_t)nb_med, (T.cnt[kMedium] + (blockDim.x >> 6) - 1) / (blockDim.x >> 6));
+    const int64_t a_l = min(nb_large, T.cnt[kLarge]);
+    int64_t r;
+    if (b < nb_small) r = b < a_s ? b : -1;
+    else if (b < nb_small + nb_med) r = b - nb_small < a_m ? a_s + (b - nb_small) : -1;
+    else r = b - nb_small - nb_med < a_l ? a_s + a_m + (b - nb_small - nb_med) : -1;
+    if (r < 0) return;  // uniform over the workgroup
+    rank = (unsigned)r;
+    nactive = (unsigned)(a_s + a_m + a_l);
     const Stage S = stage_open(lds);
     unsigned long long tc[2];
-    td_level(G, td_level_state(c), S, blockIdx.x, gridDim.x, nb_small, nb_med, tc);
+    td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med, tc);
     counts[0] = tc[0];
     counts[1] = tc[1];
   } else {
     bu_level(G, c, lds, counts);
   }
-  end_level<kPartials>(G, mode, counts);
+  end_level<kPartials>(G, mode, counts, rank, nactive);
 }
 
 // Frontier conversion before a level whose direction differs from the one
@@ -1137,20 +1164,31 @@ int wait_final(bfs_graph *g, hipStream_t st, uint32_t seq, bool *published) {
 // Waits until the device has published level state number `seq` in the
 // host-mapped mirror (polling; the stream is checked now and then so that a
 // device error ends the wait), then copies it to *out.
+// Copies the mirror once it holds publication `seq` or a later one: the
+// copy is retried if the device started another publication meanwhile
+// (its number is written before the fields, the completed number after).
 int wait_published(bfs_graph *g, hipStream_t st, uint32_t seq, Ctl *out) {
   volatile uint32_t *p = &g->ctl_host->seq;
+  volatile uint32_t *wip = &g->ctl_host->seq_wip;
   for (uint64_t spin = 0;; ++spin) {
-    if (__atomic_load_n(p, __ATOMIC_ACQUIRE) == seq) break;
+    const uint32_t got = __atomic_load_n(p, __ATOMIC_ACQUIRE);
+    if ((int32_t)(got - seq) >= 0) {
+      std::memcpy(out, g->ctl_host, sizeof(Ctl));
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      if (__atomic_load_n(wip, __ATOMIC_ACQUIRE) == got) {
+        out->seq = got;
+        return BFS_OK;
+      }
+      continue;  // torn: a newer publication is being written
+    }
     if ((spin & 1023) == 1023) {
       const hipError_t q = hipStreamQuery(st);
       if (q != hipSuccess && q != hipErrorNotReady)
         return fail(BFS_ERR_DEVICE, "level kernels failed: %s", hipGetErrorString(q));
-      if (q == hipSuccess && __atomic_load_n(p, __ATOMIC_ACQUIRE) != seq)
+      if (q == hipSuccess && (int32_t)(__atomic_load_n(p, __ATOMIC_ACQUIRE) - seq) < 0)
         return fail(BFS_ERR_DEVICE, "the device did not publish level %u", seq);
     }
   }
-  std::memcpy(out, g->ctl_host, sizeof(Ctl));
-  return BFS_OK;
 }
 
 hipEvent_t level_event(bfs_graph *g, size_t i) {
@@ -1277,6 +1315,67 @@ int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
   return BFS_OK;
 }
 
+// Lookahead loop: the host keeps `ahead` levels enqueued beyond the last
+// one the device has published, each as [conversion, level] with the
+// direction read on the device (the kernels of levels past the end exit at
+// once), so the device never waits for the host between levels; per-level
+// HIP events bracket every level kernel.
+template <class RowT>
+int queued_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy, std::vector<float> &level_ms) {
+  const Shapes S = shapes_of(g);
+  const bool hybrid = policy != BFS_POLICY_TD_ONLY;
+  const bool timing = g->params.collect_timing != 0;
+  const int ahead = g->params.queue_ahead;
+  // fixed role sizes, as in the captured loop
+  const int gb = g->params.graph_td_blocks;
+  TdRoles r;
+  r.small = blocks_for(g->n, S.bs, gb);
+  r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, std::max(1, gb / 2)) : 0;
+  r.large = g->max_degree > G.t2 ? std::max(1, gb / 2) : 0;
+  const int blocks = hybrid ? std::max(r.small + r.med + r.large, S.bu_blocks) : r.small + r.med + r.large;
+  const uint32_t base = g->pub_seq;  // init published base + 1, level L publishes base + L + 2
+  int enq = 0;
+  int rc;
+  auto enqueue = [&]() -> int {
+    if (hybrid) hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, st, G);
+    if (timing) {
+      hipEvent_t e0 = level_event(g, 2 * (size_t)enq), e1 = level_event(g, 2 * (size_t)enq + 1);
+      if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
+      BFS_HIP(hipEventRecord(e0, st));
+      launch_level(G, S, kAnyDir, blocks, r, st);
+      BFS_HIP(hipEventRecord(e1, st));
+    } else {
+      launch_level(G, S, kAnyDir, blocks, r, st);
+    }
+    BFS_HIP(hipGetLastError());
+    ++enq;
+    return BFS_OK;
+  };
+  int levels = 0;
+  for (int seen = 0;;) {  // seen: the next level whose publication is awaited
+    while (enq < seen + ahead)
+      if ((rc = enqueue())) return rc;
+    Ctl h;
+    if ((rc = wait_published(g, st, base + 2 + (uint32_t)seen, &h))) return rc;
+    const int level = (int)(h.seq - base - 2);  // the latest published level
+    if (h.done) {
+      levels = level + 1;
+      break;
+    }
+    seen = level + 1;
+  }
+  if (timing) {
+    level_ms.clear();
+    BFS_HIP(hipEventSynchronize(g->level_events[2 * (size_t)levels - 1]));
+    for (int l = 0; l < levels; ++l) {
+      float ms = 0.f;
+      BFS_HIP(hipEventElapsedTime(&ms, g->level_events[2 * l], g->level_events[2 * l + 1]));
+      level_ms.push_back(ms);
+    }
+  }
+  return BFS_OK;
+}
+
 // Persistent top-down loop: one cooperative launch runs every level.
 template <class RowT>
 int persistent_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st) {
@@ -1313,7 +1412,7 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   hipStream_t st = g->stream;
   const int policy = resolved_policy(g);
   int loop = g->params.loop;
-  if (loop == BFS_LOOP_AUTO) loop = (policy == BFS_POLICY_TD_ONLY) ? BFS_LOOP_GRAPH : BFS_LOOP_HOST;
+  if (loop == BFS_LOOP_AUTO) loop = BFS_LOOP_GRAPH;
   if (loop == BFS_LOOP_PERSISTENT && policy != BFS_POLICY_TD_ONLY) loop = BFS_LOOP_HOST;
   const int bs = g->params.block_size;
   g->pub_seq = std::max(g->pub_seq, __atomic_load_n(&g->ctl_host->seq, __ATOMIC_ACQUIRE));
@@ -1321,11 +1420,12 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   hipLaunchKernelGGL(k_init<RowT>, dim3(blocks_for(std::max(g->n, g->words), bs, 4096)), dim3(bs), 0, st,
                      G, s, dist, parent, (int32_t)policy, g->params.alpha, g->params.beta, g->nnz,
                      g->rec_cap, g->ctl_host_dev, g->pub_seq,
-                     (int32_t)(loop == BFS_LOOP_HOST ? kPubEvery : kPubFinal));
+                     (int32_t)(loop == BFS_LOOP_HOST || loop == BFS_LOOP_QUEUED ? kPubEvery : kPubFinal));
   BFS_HIP(hipGetLastError());
   std::vector<float> level_ms;
   int rc = loop == BFS_LOOP_HOST    ? host_loop(g, G, st, level_ms)
            : loop == BFS_LOOP_GRAPH ? graph_loop(g, G, st, policy)
+           : loop == BFS_LOOP_QUEUED ? queued_loop(g, G, st, policy, level_ms)
                                     : persistent_loop(g, G, st);
   if (rc) {
     g->pub_seq += 1u << 20;  // keep later runs clear of anything this run may still publish

@@ -101,3 +101,10 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         L.load_library()
+
+
+def test_loop_param_defaults(lib):
+    """Defaults of the queued-loop lookahead and the bottom-up grid."""
+    import paper_2503_00430_amd._lib as L
+    d = L.bfs_default_params()
+    assert d["queue_ahead"] == 2 and d["bu_blocks"] == 0

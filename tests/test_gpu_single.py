@@ -24,7 +24,7 @@ def bfs():
 
 @pytest.mark.parametrize("name", sorted(graphs.CLOSED_FORMS))
 @pytest.mark.parametrize("policy", sorted(POLICIES))
-@pytest.mark.parametrize("loop", [1, 2, 3])
+@pytest.mark.parametrize("loop", [1, 2, 3, 4])
 def test_closed_forms(bfs, name, policy, loop):
     g, f = graphs.CLOSED_FORMS[name]()
     say("closed form", name, policy, "loop", loop)
@@ -55,7 +55,7 @@ def test_rmat16_config(bfs, rmat16):
 
 
 @pytest.mark.parametrize("policy", sorted(POLICIES))
-@pytest.mark.parametrize("loop", [1, 2])
+@pytest.mark.parametrize("loop", [1, 2, 4])
 @pytest.mark.parametrize("rp32", [False, True])
 def test_rmat16_policies_loops(bfs, rmat16, policy, loop, rp32):
     g = rmat16
@@ -124,7 +124,7 @@ def test_edge_cases(bfs):
     gh.close()
 
 
-@pytest.mark.parametrize("loop", [1, 2, 3])
+@pytest.mark.parametrize("loop", [1, 2, 3, 4])
 def test_hub_chunks(bfs, loop):
     """A hub of degree 50 000 (far above td_block_degree) as source and as a
     discovered vertex: its row is split into workgroup chunks."""
@@ -183,6 +183,9 @@ def test_validate_flags(bfs):
         bfs.bfs_run(gh, 2, d)
     with pytest.raises(bfs.BfsError):
         bfs.bfs_set_params(gh, block_size=100)
+    for bad in ({"queue_ahead": 65}, {"queue_ahead": -1}, {"bu_blocks": 1025}, {"loop": 5}):
+        with pytest.raises(bfs.BfsError):
+            bfs.bfs_set_params(gh, **bad)
     gh.close()
 
 
@@ -284,14 +287,16 @@ def test_rmat16_bu_blocks(rmat16, bu_blocks, sort):
 
 
 @pytest.mark.parametrize("policy", [1, 3])
-def test_level_timing(rmat16, policy):
-    """collect_timing: every level of a host-loop run gets a device time."""
+@pytest.mark.parametrize("loop,ahead", [(1, 2), (4, 1), (4, 2), (4, 16)])
+def test_level_timing(rmat16, policy, loop, ahead):
+    """collect_timing: every level of a host-loop or queued-loop run gets a
+    device time (queued lookahead shorter and longer than the search)."""
     bfs = library()
     g = rmat16
-    say("rmat16 level timing, policy", policy)
+    say("rmat16 level timing, policy", policy, "loop", loop, "ahead", ahead)
     gh = upload(g)
-    bfs.bfs_set_params(gh, policy=policy, loop=1, collect_timing=1)
+    bfs.bfs_set_params(gh, policy=policy, loop=loop, queue_ahead=ahead, collect_timing=1)
     for s in graphgen.sources(g, 4, seed=29):
         _, _, run, levels = check_single(g, gh, s)
-        assert run["loop"] == 1 and all(lv["ms"] > 0 for lv in levels), levels
+        assert run["loop"] == loop and all(lv["ms"] > 0 for lv in levels), levels
     gh.close()
