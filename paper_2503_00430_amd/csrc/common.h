@@ -17,7 +17,10 @@ namespace bfsmi {
 constexpr int kWave = 64;
 
 enum Dir : int32_t { kTD = 0, kBU = 1 };
-enum Conv : int32_t { kConvNone = 0, kConvQ2B = 1, kConvB2Q = 2 };
+// How the frontier of the level about to run is held: as queues (the usual
+// top-down form) or, right after a switch back from bottom-up, as the bitmap
+// the bottom-up level wrote.
+enum Conv : int32_t { kConvNone = 0, kConvB2Q = 2 };
 enum Bucket : int32_t { kSmall = 0, kMedium = 1, kLarge = 2 };
 enum Publish : int32_t { kPubEvery = 0, kPubFinal = 1 };
 
@@ -38,7 +41,7 @@ struct alignas(256) Ctl {
   int32_t done;    // nonzero once a level found nothing
   int32_t qcur;    // queue set holding the current frontier
   int32_t bcur;    // bitmap holding the current frontier
-  int32_t conv;    // frontier conversion to perform before `level` runs
+  int32_t conv;    // kConvB2Q: a top-down `level` reads its frontier from the bitmap
   int32_t policy;  // resolved bfs_policy (never AUTO)
   int32_t alpha, beta;
   int32_t rec_cap;  // capacity of the LevelRec array

@@ -241,7 +241,8 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
   const uint64_t sb = 1ull << (s & 63);
   for (int64_t w = tid; w < G.words; w += stride) {
     G.vis[w] = G.iso[w] | (w == sw ? sb : 0ull);
-    G.bm[0][w] = 0;
+    // hybrid searches keep bm[0] as the current frontier bitmap from level 0
+    G.bm[0][w] = (policy != BFS_POLICY_TD_ONLY && w == sw) ? sb : 0ull;
     G.bm[1][w] = 0;
   }
   for (int64_t i = tid; i < (int64_t)kPartialsAlloc; i += stride) G.partials[i] = 0;  // and arrivals
@@ -334,7 +335,9 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   } else {
     nxt = (found * (int64_t)c->beta < c->n && found < c->n_f) ? kTD : kBU;
   }
-  c->conv = (cur == kTD && nxt == kBU) ? kConvQ2B : (cur == kBU && nxt == kTD) ? kConvB2Q : kConvNone;
+  // (top-down levels keep the frontier bitmap of hybrid searches current, so
+  // only a switch back to top-down changes how the frontier is read)
+  c->conv = (cur == kBU && nxt == kTD) ? kConvB2Q : kConvNone;
   if (c->conv == kConvB2Q)
     for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
   c->n_f = found;
@@ -382,16 +385,28 @@ __device__ void reduce_partials(unsigned long long *partials, int nblocks, unsig
 
 // Discovery step shared by the top-down roles: the lane examines edge
 // target v of frontier vertex u (when `has`), then the wavefront stages.
+// Hybrid searches keep the current frontier bitmap exact through top-down
+// levels: an expanded vertex leaves it, a discovered one enters it (the two
+// sets are disjoint, and atomics on shared words commute), so a switch to
+// bottom-up needs no conversion.  `fbm` is null for top-down-only searches.
+__device__ __forceinline__ void fbm_set(uint64_t *fbm, int32_t v) {
+  if (fbm) atomicOr(reinterpret_cast<unsigned long long *>(fbm + (v >> 6)), 1ull << (v & 63));
+}
+__device__ __forceinline__ void fbm_clear(uint64_t *fbm, int32_t u) {
+  if (fbm) atomicAnd(reinterpret_cast<unsigned long long *>(fbm + (u >> 6)), ~(1ull << (u & 63)));
+}
+
 template <class RowT>
 __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
-                                         int32_t *dist, int32_t *parent, bool has, int32_t u, int32_t v,
-                                         unsigned long long &nfound, unsigned long long &dfound) {
+                                         int32_t *dist, int32_t *parent, uint64_t *fbm, bool has, int32_t u,
+                                         int32_t v, unsigned long long &nfound, unsigned long long &dfound) {
   bool win = false;
   int64_t deg = 0;
   if (has && claim(G.vis, v)) {
     win = true;
     dist[v] = level + 1;  // plain store: the claim made this lane the only writer
     if (parent) parent[v] = u;
+    fbm_set(fbm, v);
     deg = G.head[v].x;
     nfound += 1;
     dfound += (unsigned long long)deg;
@@ -412,16 +427,66 @@ struct TdLevel {
   int32_t qcur, level;
   int64_t cnt[3];
   int32_t *dist, *parent;
+  uint64_t *fbm;       // current frontier bitmap (hybrid searches), else null
+  bool from_bitmap;    // the frontier is the bitmap of a bottom-up level
 };
 
-__device__ __forceinline__ TdLevel td_level_state(const Ctl *c) {
+template <class RowT>
+__device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl *c) {
   TdLevel t;
   t.qcur = c->qcur;
   t.level = c->level;
   for (int b = 0; b < 3; ++b) t.cnt[b] = c->qcnt[t.qcur][b];
   t.dist = c->dist;
   t.parent = c->parent;
+  t.fbm = c->policy != BFS_POLICY_TD_ONLY ? (c->bcur ? G.bm[1] : G.bm[0]) : nullptr;
+  t.from_bitmap = c->conv == kConvB2Q;
   return t;
+}
+
+// Expands frontier vertex u of the calling lane (`act`; h = its head record,
+// row0 = its row offset) one lane per vertex: the head neighbours are
+// claimed together (their visited words, the claims and the new vertices'
+// degrees are three rounds of independent requests instead of three per
+// neighbour), then the rest of the row in lock-step with the wavefront.
+// All lanes of the wavefront call it together.
+template <class RowT>
+__device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
+                                               bool act, int32_t u, const int4 &h, int64_t row0,
+                                               unsigned long long &nfound, unsigned long long &dfound) {
+  const int64_t deg = act ? h.x : 0;
+  const int32_t x[3] = {act ? h.y : -1, act ? h.z : -1, act ? h.w : -1};
+  uint64_t w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
+  bool win[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t bit = x[k] >= 0 ? 1ull << (x[k] & 63) : 0ull;
+    win[k] = false;
+    if (x[k] >= 0 && !(w[k] & bit))
+      win[k] = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (x[k] >> 6)), (unsigned long long)bit) &
+                 bit);
+  }
+  int64_t dv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (win[k]) {
+      T.dist[x[k]] = T.level + 1;  // plain store: the claim made this lane the only writer
+      if (T.parent) T.parent[x[k]] = u;
+      fbm_set(T.fbm, x[k]);
+      nfound += 1;
+      dfound += (unsigned long long)dv[k];
+    }
+    wave_stage(G, S, qn, win[k], x[k], dv[k]);
+  }
+  for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
+    const bool has = j < deg;
+    const int32_t v = has ? G.col[row0 + j] : 0;
+    td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
+  }
 }
 
 // One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
@@ -431,15 +496,12 @@ __device__ __forceinline__ TdLevel td_level_state(const Ctl *c) {
 //   the rest                      workgroup per t2-edge chunk of a larger
 //                                 vertex.
 // Ends with the staged queue entries flushed and the workgroup's counts in
-// its partials slot.  All threads of the workgroup call it.
+// `counts`.  All threads of the workgroup call it.
 template <class RowT>
 __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, const Stage &S, int blk,
                                          int nblk, int nb_small, int nb_med,
                                          unsigned long long (&counts)[2]) {
   const int qc = T.qcur, qn = qc ^ 1;
-  const int32_t level = T.level;
-  int32_t *dist = T.dist;
-  int32_t *parent = T.parent;
   const int lane = lane_id();
   const int wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
   unsigned long long nfound = 0, dfound = 0;
@@ -458,44 +520,9 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       if (act) {
         h = G.head[u];  // degree and first three neighbours
         row0 = (int64_t)G.rp[u];  // issued together with the head load
+        fbm_clear(T.fbm, u);
       }
-      const int64_t deg = h.x;
-      // The head neighbours are claimed together: their visited words, the
-      // claims and the new vertices' degrees are three rounds of independent
-      // requests instead of three per neighbour.
-      {
-        const int32_t x[3] = {h.y, h.z, h.w};
-        uint64_t w[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
-        bool win[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const uint64_t bit = x[k] >= 0 ? 1ull << (x[k] & 63) : 0ull;
-          win[k] = false;
-          if (x[k] >= 0 && !(w[k] & bit))
-            win[k] = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (x[k] >> 6)),
-                                (unsigned long long)bit) & bit);
-        }
-        int64_t dv[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if (win[k]) {
-            dist[x[k]] = level + 1;  // plain store: the claim made this lane the only writer
-            if (parent) parent[x[k]] = u;
-            nfound += 1;
-            dfound += (unsigned long long)dv[k];
-          }
-          wave_stage(G, S, qn, win[k], x[k], dv[k]);
-        }
-      }
-      for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
-        const bool has = j < deg;
-        const int32_t v = has ? G.col[row0 + j] : 0;
-        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
-      }
+      td_expand_lane(G, S, T, qn, act, u, h, row0, nfound, dfound);
       stage_flush(G, S, qn, true);
     }
   } else if (blk < nb_small + nb_med) {
@@ -506,12 +533,13 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       const int64_t i = round + wib;
       if (i < cnt) {  // uniform within the wavefront
         const int32_t u = q[i];
+        if (lane == 0) fbm_clear(T.fbm, u);
         const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
         for (int64_t b = beg; b < end; b += kWave) {
           const int64_t j = b + lane;
           const bool has = j < end;
           const int32_t v = has ? G.col[j] : 0;
-          td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+          td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
         }
       }
       stage_flush(G, S, qn, true);
@@ -524,6 +552,7 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       const uint64_t e = q[i];
       const int32_t u = (int32_t)(uint32_t)e;
       const int64_t chunk = (int64_t)(e >> 32);
+      if (chunk == 0 && threadIdx.x == 0) fbm_clear(T.fbm, u);
       const int64_t row_end = (int64_t)G.rp[u + 1];
       const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
       const int64_t end = min(row_end, beg + (int64_t)G.t2);
@@ -531,10 +560,89 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
         const int64_t j = b + lane;
         const bool has = j < end;
         const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, level, dist, parent, has, u, v, nfound, dfound);
+        td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
       }
       stage_flush(G, S, qn, true);
     }
+  }
+  stage_flush(G, S, qn);
+  counts[0] = nfound;
+  counts[1] = dfound;
+}
+
+// Top-down level whose frontier is the bitmap a bottom-up level left (the
+// level after a switch back to top-down; no conversion to queues): every
+// workgroup expands the frontier vertices of its own share of the words.  A
+// wavefront loads 64 words with one coalesced load, takes their frontier
+// bits out of the bitmap (atomically: discoveries of this level enter the
+// same words), compacts the frontier vertices into batches of 64 in an LDS
+// ring and loads their head records together; vertices of degree <= t1 are
+// expanded by their lane, larger ones by the whole wavefront, 64 neighbours
+// at a time.  `ring` is this wavefront's kCand-entry LDS ring.
+constexpr int kCandTd = 128;
+
+template <class RowT>
+__device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLevel &T, const Stage &S,
+                                                int32_t *ring, unsigned long long (&counts)[2]) {
+  const int qn = T.qcur ^ 1;
+  const int lane = lane_id();
+  unsigned long long nfound = 0, dfound = 0;
+  uint64_t *fbm = T.fbm;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
+  const int64_t per = (G.words + nw - 1) / nw;
+  const int64_t w0 = gw * per;
+  const int64_t w1 = min(G.words, w0 + per);
+  // expands the `cnt` ring entries from `head`
+  auto batch = [&](unsigned head, int cnt) {
+    const bool act = lane < cnt;
+    int32_t u = 0;
+    int4 h = make_int4(0, -1, -1, -1);
+    int64_t row0 = 0;
+    if (act) {
+      u = ring[(head + lane) & (kCandTd - 1)];
+      h = G.head[u];
+      row0 = (int64_t)G.rp[u];
+    }
+    const bool big = act && h.x > G.t1;
+    td_expand_lane(G, S, T, qn, act && !big, u, h, row0, nfound, dfound);
+    uint64_t bm = __ballot(big);
+    while (bm) {  // larger rows: the whole wavefront, 64 neighbours at a time
+      const int l = __ffsll((unsigned long long)bm) - 1;
+      bm &= bm - 1;
+      const int32_t ub = __shfl(u, l);
+      const int64_t beg = __shfl(row0, l);
+      const int64_t end = beg + __shfl(h.x, l);
+      for (int64_t b = beg; b < end; b += kWave) {
+        const int64_t j = b + lane;
+        const bool has = j < end;
+        const int32_t v = has ? G.col[j] : 0;
+        td_visit(G, S, qn, T.level, T.dist, T.parent, fbm, has, ub, v, nfound, dfound);
+      }
+    }
+  };
+  for (int64_t r = 0; r < per; r += kWave) {  // workgroup-uniform rounds of 64 words
+    const int64_t sr = w0 + r;
+    const uint64_t wd = sr + lane < w1 ? fbm[sr + lane] : 0ull;
+    if (wd) atomicAnd(reinterpret_cast<unsigned long long *>(fbm + sr + lane), ~wd);
+    uint64_t nz = __ballot(wd != 0ull);
+    unsigned ch = 0, ct = 0;  // ring head / tail (wave-uniform)
+    while (nz) {
+      const int k = __builtin_ctzll(nz);
+      nz &= nz - 1;
+      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)wd, k);
+      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(wd >> 32), k);
+      const uint64_t bits = ((uint64_t)hi << 32) | lo;
+      if ((bits >> lane) & 1ull) ring[(ct + lanes_below(bits)) & (kCandTd - 1)] = (int32_t)((sr + k) * kWave + lane);
+      ct += (unsigned)__popcll(bits);
+      if (ct - ch >= (unsigned)kWave) {
+        batch(ch, kWave);
+        ch += kWave;
+      }
+    }
+    if (ct != ch) batch(ch, (int)(ct - ch));
+    stage_flush(G, S, qn, true);
   }
   stage_flush(G, S, qn);
   counts[0] = nfound;
@@ -663,6 +771,8 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
     for (int b = 0; b < 3; ++b) T.cnt[b] = ld_agent(&c->qcnt[T.qcur][b]);
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
+    T.fbm = nullptr;  // top-down only: no frontier bitmap to keep
+    T.from_bitmap = false;
     const Stage S = stage_open(lds);
     unsigned long long counts[2];
     td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med, counts);
@@ -959,8 +1069,18 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
   unsigned long long counts[kPartials] = {0, 0, 0, 0};
   unsigned rank = blockIdx.x, nactive = gridDim.x;
   if (D == kTD || (D == kAnyDir && c->dir == kTD)) {
+    const TdLevel T = td_level_state(G, c);
+    if (T.from_bitmap) {  // every workgroup takes a share of the frontier words
+      const Stage S = stage_open(lds);
+      int32_t *ring = reinterpret_cast<int32_t *>(lds + stage_bytes(blockDim.x)) + (threadIdx.x >> 6) * kCandTd;
+      unsigned long long tc[2];
+      td_level_bitmap(G, T, S, ring, tc);
+      counts[0] = tc[0];
+      counts[1] = tc[1];
+      end_level<kPartials>(G, mode, counts, rank, nactive);
+      return;
+    }
     // only the workgroups whose role has work this level take part
-    const TdLevel T = td_level_state(c);
     const int64_t b = blockIdx.x;
     const int64_t nb_large = (int64_t)gridDim.x - nb_small - nb_med;
     const int64_t a_s = min((int64_t)nb_small, (T.cnt[kSmall] + blockDim.x - 1) / blockDim.x);
@@ -982,72 +1102,6 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
     bu_level(G, c, lds, counts);
   }
   end_level<kPartials>(G, mode, counts, rank, nactive);
-}
-
-// Frontier conversion before a level whose direction differs from the one
-// before it (one kernel serves both directions of change):
-//   queue -> bitmap: the bit of every frontier vertex is set in the current
-//     frontier bitmap (kept all-zero while levels run top-down);
-//   bitmap -> queue: the frontier bitmap is compacted into degree-bucketed
-//     queues and cleared on the way (so it is all-zero again for the next
-//     queue -> bitmap conversion).  A wavefront loads 64 words with one
-//     coalesced load and visits only the nonzero ones.
-template <class RowT>
-__global__ void k_conv(DevG<RowT> G) {
-  const Ctl *c = G.ctl;
-  const int32_t conv = c->conv;
-  if (c->done || conv == kConvNone) return;
-  const int q = c->qcur;
-  uint64_t *bm = c->bcur ? G.bm[1] : G.bm[0];
-  if (conv == kConvQ2B) {
-    const int64_t c0 = c->qcnt[q][kSmall], c1 = c->qcnt[q][kMedium], c2 = c->qcnt[q][kLarge];
-    const int32_t *qs = q ? G.qs[1] : G.qs[0];
-    const int32_t *qm = q ? G.qm[1] : G.qm[0];
-    const uint64_t *ql = q ? G.ql[1] : G.ql[0];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c0 + c1 + c2; i += stride) {
-      int32_t v;
-      if (i < c0) {
-        v = qs[i];
-      } else if (i < c0 + c1) {
-        v = qm[i - c0];
-      } else {
-        const uint64_t e = ql[i - c0 - c1];
-        if (e >> 32) continue;  // chunk > 0 of a vertex already counted
-        v = (int32_t)(uint32_t)e;
-      }
-      atomicOr(reinterpret_cast<unsigned long long *>(bm + (v >> 6)), 1ull << (v & 63));
-    }
-    return;
-  }
-  extern __shared__ __align__(16) char lds[];
-  const Stage S = stage_open(lds);
-  const int lane = lane_id();
-  const int64_t wpb = blockDim.x >> 6;
-  const int64_t nw = (int64_t)gridDim.x * wpb;
-  const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
-  const int64_t per = (G.words + nw - 1) / nw;
-  const int64_t w0 = gw * per;
-  const int64_t w1 = min(G.words, w0 + per);
-  for (int64_t r = 0; r < per; r += kWave) {  // workgroup-uniform rounds of 64 words
-    const int64_t sr = w0 + r;
-    const uint64_t word = sr + lane < w1 ? bm[sr + lane] : 0ull;
-    if (word) bm[sr + lane] = 0;
-    uint64_t nz = __ballot(word != 0ull);
-    while (nz) {
-      const int k = __builtin_ctzll(nz);
-      nz &= nz - 1;
-      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)word, k);
-      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(word >> 32), k);
-      const uint64_t wk = ((uint64_t)hi << 32) | lo;
-      const int64_t v = (sr + k) * kWave + lane;
-      const bool in = (wk >> lane) & 1ull;
-      const int64_t deg = in ? (int64_t)G.head[v].x : 0;
-      wave_stage(G, S, q, in, (int32_t)v, deg);
-    }
-    stage_flush(G, S, q, true);
-  }
-  stage_flush(G, S, q);
 }
 
 // Head records: degree and the first three neighbours (-1 where the row is
@@ -1100,11 +1154,10 @@ DevG<RowT> make_devg(bfs_graph *g) {
 struct Shapes {
   int bs;            // threads per workgroup
   int wpb;           // wavefronts per workgroup
-  int words_blocks;  // grid of the bitmap -> queue conversion
+  int words_blocks;  // one word per wavefront, up to kMaxBlocks workgroups
   int bu_blocks;     // grid of the bottom-up kernel
   size_t lds;        // dynamic LDS of the staging kernels
   size_t level_lds;  // dynamic LDS of the level kernel
-  int conv_blocks;   // grid of the conversion kernel
 };
 
 Shapes shapes_of(const bfs_graph *g) {
@@ -1114,8 +1167,7 @@ Shapes shapes_of(const bfs_graph *g) {
   s.words_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
   s.bu_blocks = g->params.bu_blocks > 0 ? g->params.bu_blocks : s.words_blocks;
   s.lds = stage_bytes(s.bs);
-  s.level_lds = std::max(s.lds, bu_lds_bytes(s.bs));
-  s.conv_blocks = std::min(s.words_blocks, 128);
+  s.level_lds = std::max(s.lds + (size_t)s.wpb * kCandTd * sizeof(int32_t), bu_lds_bytes(s.bs));
   return s;
 }
 
@@ -1227,8 +1279,6 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       return rc;
     }
     if (h.done) break;
-    if (h.conv != kConvNone)
-      hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, st, G);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing) {  // the events bracket the level's direction kernel only
       e0 = level_event(g, nev++);
@@ -1236,13 +1286,10 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
       BFS_HIP(hipEventRecord(e0, st));
     }
-    if (h.dir == kTD) {
-      int64_t c0 = h.qcnt[h.qcur][0], c1 = h.qcnt[h.qcur][1], c2 = h.qcnt[h.qcur][2];
-      if (h.conv == kConvB2Q) {  // counts are produced on the device by the conversion
-        c0 = c1 = h.n_f;
-        c2 = g->max_degree > G.t2 ? h.m_f / G.t2 + h.n_f : 0;
-      }
-      const TdRoles r = td_roles(S, c0, c1, c2);
+    if (h.dir == kTD && h.conv == kConvB2Q) {  // frontier read from the bitmap, word-parallel
+      launch_level(G, S, kTD, S.bu_blocks, TdRoles{0, 0, 0}, st);
+    } else if (h.dir == kTD) {
+      const TdRoles r = td_roles(S, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qcnt[h.qcur][2]);
       launch_level(G, S, kTD, r.small + r.med + r.large, r, st);
     } else {
       launch_level(G, S, kBU, S.bu_blocks, TdRoles{0, 0, 0}, st);
@@ -1265,7 +1312,7 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
 }
 
 // Captured level loop: `K` levels of fixed-shape launches whose kernels read
-// the direction / conversion / done flags from the control block; replayed
+// the direction / frontier-form / done flags from the control block; replayed
 // until done.
 template <class RowT>
 int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
@@ -1278,13 +1325,12 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
   r.small = blocks_for(g->n, S.bs, gb);
   r.med = g->max_degree > G.t1 ? blocks_for(g->n, S.wpb, std::max(1, gb / 2)) : 0;
   r.large = g->max_degree > G.t2 ? std::max(1, gb / 2) : 0;
-  // a hybrid level is [conversion, level]; the level kernel's grid serves
-  // both directions (extra workgroups join the per-chunk top-down role)
+  // one level kernel per level; for hybrid searches its grid serves both
+  // directions (extra workgroups join the per-chunk top-down role)
   const int blocks = hybrid ? std::max(r.small + r.med + r.large, S.bu_blocks) : r.small + r.med + r.large;
   release_graph_exec(g);
   BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int l = 0; l < K; ++l) {
-    if (hybrid) hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, cs, G);
     launch_level(G, S, kAnyDir, blocks, r, cs);
   }
   hipGraph_t graph = nullptr;
@@ -1316,7 +1362,7 @@ int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
 }
 
 // Lookahead loop: the host keeps `ahead` levels enqueued beyond the last
-// one the device has published, each as [conversion, level] with the
+// one the device has published, each as one level kernel with the
 // direction read on the device (the kernels of levels past the end exit at
 // once), so the device never waits for the host between levels; per-level
 // HIP events bracket every level kernel.
@@ -1337,7 +1383,6 @@ int queued_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy, s
   int enq = 0;
   int rc;
   auto enqueue = [&]() -> int {
-    if (hybrid) hipLaunchKernelGGL(k_conv<RowT>, dim3(S.conv_blocks), dim3(S.bs), S.lds, st, G);
     if (timing) {
       hipEvent_t e0 = level_event(g, 2 * (size_t)enq), e1 = level_event(g, 2 * (size_t)enq + 1);
       if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
