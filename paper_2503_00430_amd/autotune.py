@@ -37,6 +37,7 @@ SINGLE_SPACE = {
     "td_block_degree": [512, 1024, 2048, 4096],
     "block_size": [256, 512, 1024],
     "bu_blocks": [0, 256, 512],
+    "graph_td_blocks": [64, 128, 256, 512],
 }
 GRAPH_SPACE = {
     "graph_td_blocks": [16, 32, 64, 128, 256],

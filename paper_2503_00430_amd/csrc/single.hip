@@ -573,12 +573,15 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
 // Top-down level whose frontier is the bitmap a bottom-up level left (the
 // level after a switch back to top-down; no conversion to queues): every
 // workgroup expands the frontier vertices of its own share of the words.  A
-// wavefront loads 64 words with one coalesced load, takes their frontier
-// bits out of the bitmap (atomically: discoveries of this level enter the
-// same words), compacts the frontier vertices into batches of 64 in an LDS
-// ring and loads their head records together; vertices of degree <= t1 are
-// expanded by their lane, larger ones by the whole wavefront, 64 neighbours
-// at a time.  `ring` is this wavefront's kCand-entry LDS ring.
+// wavefront loads 64 words with one coalesced load, compacts their set bits
+// into batches of 64 in an LDS ring and loads the head records together.
+// Discoveries of this level enter the same bitmap while it is read, so a set
+// bit is a frontier vertex only if its distance is this level's (written by
+// an earlier level; a vertex found now holds level + 1, or -1 if that store
+// is not yet visible); only those are expanded and taken out of the bitmap.
+// Vertices of degree <= t1 are expanded by their lane, larger ones by the
+// whole wavefront, 64 neighbours at a time.  `ring` is this wavefront's
+// kCandTd-entry LDS ring.
 constexpr int kCandTd = 128;
 
 template <class RowT>
@@ -596,15 +599,19 @@ __device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLev
   const int64_t w1 = min(G.words, w0 + per);
   // expands the `cnt` ring entries from `head`
   auto batch = [&](unsigned head, int cnt) {
-    const bool act = lane < cnt;
+    bool act = lane < cnt;
     int32_t u = 0;
     int4 h = make_int4(0, -1, -1, -1);
     int64_t row0 = 0;
+    int32_t du = -1;
     if (act) {
       u = ring[(head + lane) & (kCandTd - 1)];
+      du = T.dist[u];
       h = G.head[u];
       row0 = (int64_t)G.rp[u];
     }
+    act = act && du == T.level;  // a frontier vertex, not one found this level
+    if (act) fbm_clear(fbm, u);
     const bool big = act && h.x > G.t1;
     td_expand_lane(G, S, T, qn, act && !big, u, h, row0, nfound, dfound);
     uint64_t bm = __ballot(big);
@@ -625,7 +632,6 @@ __device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLev
   for (int64_t r = 0; r < per; r += kWave) {  // workgroup-uniform rounds of 64 words
     const int64_t sr = w0 + r;
     const uint64_t wd = sr + lane < w1 ? fbm[sr + lane] : 0ull;
-    if (wd) atomicAnd(reinterpret_cast<unsigned long long *>(fbm + sr + lane), ~wd);
     uint64_t nz = __ballot(wd != 0ull);
     unsigned ch = 0, ct = 0;  // ring head / tail (wave-uniform)
     while (nz) {

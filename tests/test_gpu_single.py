@@ -300,3 +300,34 @@ def test_level_timing(rmat16, policy, loop, ahead):
         _, _, run, levels = check_single(g, gh, s)
         assert run["loop"] == loop and all(lv["ms"] > 0 for lv in levels), levels
     gh.close()
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    return graphgen.rmat(20)
+
+
+@pytest.fixture(scope="module")
+def rmat20_hub_first(rmat20):
+    return hub_first(rmat20)
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+@pytest.mark.parametrize("sort", [False, True])
+def test_rmat20_repeated_full_parity(rmat20, rmat20_hub_first, policy, sort):
+    """RMAT scale 20 (a million vertices: every wavefront of the level
+    kernels busy at once), hybrid policies whose schedules switch back to
+    top-down, each source run three times, every run compared in full with
+    the oracle.  Races between wavefronts of one level show up here as runs
+    that differ."""
+    bfs = library()
+    g = rmat20
+    say("rmat20 repeated parity, policy", policy, "sorted", sort)
+    gh = upload(g, bfs.BFS_SORT_NEIGHBORS if sort else 0)
+    bfs.bfs_set_params(gh, policy=policy)
+    order = rmat20_hub_first if sort else None
+    for s in graphgen.sources(g, 6, seed=41):
+        ref = oracle.bfs(g, s, want_parent=False)[0]
+        for rep in range(3):
+            check_single(g, gh, s, ref=ref, full_validate=(rep == 0), scan_order=order)
+    gh.close()
