@@ -96,7 +96,7 @@ static void destroy(bfs_graph *g) {
   DeviceGuard dg(g->device);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   release_graph_exec(g);
-  void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
+  void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->headc, g->hrank, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
                   g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->ctl, g->recs, g->partials,
                   g->ms.seen, g->ms.front, g->ms.next, g->ms.counters};
   for (void *p : ptrs) free_dev(p);
@@ -260,6 +260,15 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     g->max_degree = std::max(g->max_degree, d);
   }
   for (int64_t v = n; v < g->words * 64; ++v) iso[v >> 6] |= 1ull << (v & 63);
+  // per-word ranks into the compacted head records of non-isolated vertices
+  std::vector<uint32_t> hrank(g->words);
+  {
+    uint64_t r = 0;
+    for (int64_t w = 0; w < g->words; ++w) {
+      hrank[w] = (uint32_t)r;
+      r += (uint64_t)__builtin_popcountll(~iso[w]);
+    }
+  }
   if (g->max_degree > INT32_MAX) {
     delete g;
     return fail(BFS_ERR_INVALID_ARG, "a row has more than 2^31 - 1 entries");
@@ -290,6 +299,8 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   ALLOC(g->col, nnz);
   ALLOC(g->iso, g->words);
   ALLOC(g->head, n);
+  ALLOC(g->headc, std::max<int64_t>(1, n - g->isolated));
+  ALLOC(g->hrank, g->words);
   ALLOC(g->vis, g->words);
   ALLOC(g->bm[0], g->words);
   ALLOC(g->bm[1], g->words);
@@ -323,6 +334,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   }
   if (e == hipSuccess && nnz > 0) e = hipMemcpy(g->col, col_idx, sizeof(int32_t) * nnz, kind);
   if (e == hipSuccess) e = hipMemcpy(g->iso, iso.data(), sizeof(uint64_t) * g->words, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(g->hrank, hrank.data(), sizeof(uint32_t) * g->words, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(g->ctl, 0, sizeof(Ctl));
   if (e == hipSuccess) e = hipMemset(g->partials, 0, sizeof(unsigned long long) * kPartialsAlloc);
   if (e == hipSuccess) e = hipEventCreate(&g->ev_start);

@@ -88,6 +88,8 @@ struct DevG {
   const int32_t *col;
   const uint64_t *iso;  // bit set: vertex has degree 0, or id >= n (tail of last word)
   const int4 *head;     // per vertex: {degree, first three neighbours or -1}
+  const int4 *headc;    // the same records for the non-isolated vertices only, in id order
+  const uint32_t *hrank;  // per word: non-isolated vertices in the words before it
   uint64_t *vis;        // visited bitmap
   uint64_t *bm[2];      // frontier bitmaps (current / next alternate)
   int32_t *qs[2];       // queue sets: small-degree vertices
@@ -119,6 +121,8 @@ struct bfs_graph {
   int32_t *col = nullptr;
   uint64_t *iso = nullptr;
   int4 *head = nullptr;  // {degree, first three neighbours or -1} per vertex
+  int4 *headc = nullptr;  // head records of the non-isolated vertices only, in id order
+  uint32_t *hrank = nullptr;  // per word: count of non-isolated vertices in earlier words
   uint64_t *vis = nullptr;
   uint64_t *bm[2] = {nullptr, nullptr};
   int32_t *qs[2] = {nullptr, nullptr};

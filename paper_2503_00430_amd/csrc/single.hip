@@ -450,37 +450,51 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
 // degrees are three rounds of independent requests instead of three per
 // neighbour), then the rest of the row in lock-step with the wavefront.
 // All lanes of the wavefront call it together.
-template <class RowT>
-__device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
-                                               bool act, int32_t u, const int4 &h, int64_t row0,
+// Claims K neighbours x[k] (-1: none) of frontier vertex u[k] per lane
+// together: their visited words, the claims and the new vertices' degrees
+// are three rounds of K independent requests instead of three per
+// neighbour.  All lanes of the wavefront call it together.
+template <int K, class RowT>
+__device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
+                                               const int32_t (&x)[K], const int32_t (&u)[K],
                                                unsigned long long &nfound, unsigned long long &dfound) {
-  const int64_t deg = act ? h.x : 0;
-  const int32_t x[3] = {act ? h.y : -1, act ? h.z : -1, act ? h.w : -1};
-  uint64_t w[3];
+  uint64_t w[K];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
-  bool win[3];
+  for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
+  bool win[K];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < K; ++k) {
     const uint64_t bit = x[k] >= 0 ? 1ull << (x[k] & 63) : 0ull;
     win[k] = false;
     if (x[k] >= 0 && !(w[k] & bit))
       win[k] = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (x[k] >> 6)), (unsigned long long)bit) &
                  bit);
   }
-  int64_t dv[3];
+  int32_t dv[K];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
+  for (int k = 0; k < K; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < K; ++k) {
     if (win[k]) {
       T.dist[x[k]] = T.level + 1;  // plain store: the claim made this lane the only writer
-      if (T.parent) T.parent[x[k]] = u;
+      if (T.parent) T.parent[x[k]] = u[k];
       fbm_set(T.fbm, x[k]);
       nfound += 1;
       dfound += (unsigned long long)dv[k];
     }
-    wave_stage(G, S, qn, win[k], x[k], dv[k]);
+    wave_stage(G, S, qn, win[k], x[k], (int64_t)dv[k]);
+  }
+}
+
+template <class RowT>
+__device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
+                                               bool act, int32_t u, const int4 &h, int64_t row0,
+                                               unsigned long long &nfound, unsigned long long &dfound) {
+  const int64_t deg = act ? h.x : 0;
+  {
+    const int32_t x[3] = {act ? h.y : -1, act ? h.z : -1, act ? h.w : -1};
+    const int32_t uu[3] = {u, u, u};
+    td_claim_batch<3>(G, S, T, qn, x, uu, nfound, dfound);
   }
   for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
     const bool has = j < deg;
@@ -488,6 +502,8 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
     td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
   }
 }
+
+constexpr int kTdUnroll = 2;  // neighbours per lane per step in the wavefront / workgroup roles
 
 // One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
 //   [0, nb_small)                 thread per vertex of degree <= t1;
@@ -535,11 +551,15 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
         const int32_t u = q[i];
         if (lane == 0) fbm_clear(T.fbm, u);
         const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
-        for (int64_t b = beg; b < end; b += kWave) {
-          const int64_t j = b + lane;
-          const bool has = j < end;
-          const int32_t v = has ? G.col[j] : 0;
-          td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
+        for (int64_t b = beg; b < end; b += (int64_t)kWave * kTdUnroll) {
+          int32_t x[kTdUnroll], uu[kTdUnroll];
+#pragma unroll
+          for (int q = 0; q < kTdUnroll; ++q) {
+            const int64_t j = b + q * kWave + lane;
+            x[q] = j < end ? G.col[j] : -1;
+            uu[q] = u;
+          }
+          td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
         }
       }
       stage_flush(G, S, qn, true);
@@ -556,11 +576,16 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       const int64_t row_end = (int64_t)G.rp[u + 1];
       const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
       const int64_t end = min(row_end, beg + (int64_t)G.t2);
-      for (int64_t b = beg + wib * kWave; b < end; b += blockDim.x) {
-        const int64_t j = b + lane;
-        const bool has = j < end;
-        const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
+      // kTdUnroll neighbours per lane per step, each step's ids coalesced
+      for (int64_t b = beg + wib * kWave * kTdUnroll; b < end; b += (int64_t)blockDim.x * kTdUnroll) {
+        int32_t x[kTdUnroll], uu[kTdUnroll];
+#pragma unroll
+        for (int q = 0; q < kTdUnroll; ++q) {
+          const int64_t j = b + q * kWave + lane;
+          x[q] = j < end ? G.col[j] : -1;
+          uu[q] = u;
+        }
+        td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
       }
       stage_flush(G, S, qn, true);
     }
@@ -835,6 +860,9 @@ constexpr int kDefer = 128;  // deferred ring: < 64 waiting + 64 from one batch
 
 struct BuWaveLds {
   int32_t cand[kCand];
+  int32_t crank[kCand];  // the candidate's index in the compacted head records
+  uint64_t live[kWave];  // the run's non-isolated masks
+  uint32_t rank[kWave];  // and compacted-record offsets, one per word
   int32_t dv[kDefer];
   int32_t ddeg[kDefer];
   uint64_t mask[kWave];
@@ -846,9 +874,11 @@ __device__ __forceinline__ bool front_bit(const uint32_t *front, int32_t x) {
   return (front[x >> 5] >> (x & 31)) & 1u;
 }
 
-// Per-lane counters of a bottom-up level.
+// Per-lane counters of a bottom-up level (a lane handles far fewer than
+// 2^32 candidates; degree sums need 64 bits).
 struct BuCount {
-  unsigned long long found = 0, fdeg = 0, scan = 0, exam = 0;
+  uint32_t found = 0, scan = 0;
+  unsigned long long fdeg = 0, exam = 0;
 };
 
 // Scans `cnt` (<= 64) deferred rows starting at ring slot `head`, one per
@@ -1012,6 +1042,8 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
   for (int64_t sr = gw * per; sr < w_end; sr += kWave) {
     const int nwd = (int)min((int64_t)kWave, w_end - sr);
     const uint64_t my_vis = lane < nwd ? G.vis[sr + lane] : ~0ull;
+    W.live[lane] = lane < nwd ? ~G.iso[sr + lane] : 0ull;  // non-isolated vertices
+    W.rank[lane] = lane < nwd ? G.hrank[sr + lane] : 0u;
     W.mask[lane] = 0;
     uint64_t act = __ballot(my_vis != ~0ull);  // words with an unvisited vertex
     unsigned ch = 0, ct = 0;                   // candidate ring head / tail (uniform)
@@ -1026,7 +1058,11 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
         const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)my_vis, k);
         const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(my_vis >> 32), k);
         const uint64_t un = ~(((uint64_t)hi << 32) | lo);  // its unvisited vertices
-        if ((un >> lane) & 1ull) W.cand[(ct + lanes_below(un)) & (kCand - 1)] = (int32_t)((sr + k) * kWave + lane);
+        if ((un >> lane) & 1ull) {
+          const unsigned slot = (ct + lanes_below(un)) & (kCand - 1);
+          W.cand[slot] = (int32_t)((sr + k) * kWave + lane);
+          W.crank[slot] = (int32_t)(W.rank[k] + lanes_below(W.live[k]));
+        }
         ct += (unsigned)__popcll(un);
         if (ct - ch < (unsigned)kWave && act) continue;  // uniform
       }
@@ -1038,7 +1074,7 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
       int4 bh = make_int4(0, 0, -1, -1);
       if (lane < cnt) {
         bv = W.cand[(ch + lane) & (kCand - 1)];
-        bh = G.head[bv];
+        bh = G.headc[W.crank[(ch + lane) & (kCand - 1)]];
       }
       ch += cnt;
       if (pc) bu_resolve(G, W, pv, ph, pc, front, sr, level, dist, parent, dh, dc, cnt == 0, C);
@@ -1123,6 +1159,24 @@ __global__ void k_build_head(const RowT *rp, const int32_t *col, int4 *head, int
   }
 }
 
+// Compacted head records: the record of the r-th non-isolated vertex (in
+// id order) at index r, so a bottom-up level whose candidates are dense
+// among the non-isolated vertices reads whole lines of records it uses.
+// One thread per 64-vertex word.
+__global__ void k_build_headc(const int4 *head, const uint64_t *iso, const uint32_t *hrank, int4 *headc,
+                              int64_t words) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint64_t live = ~iso[w];
+    uint32_t r = hrank[w];
+    while (live) {
+      const int b = __builtin_ctzll(live);
+      live &= live - 1;
+      headc[r++] = head[w * kWave + b];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -1148,6 +1202,8 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.ctl = g->ctl;
   G.recs = g->recs;
   G.partials = g->partials;
+  G.headc = g->headc;
+  G.hrank = g->hrank;
   G.n = g->n;
   G.words = g->words;
   G.t1 = g->params.td_wave_degree;
@@ -1531,6 +1587,8 @@ int build_head(bfs_graph *g) {
   else
     hipLaunchKernelGGL(k_build_head<int32_t>, dim3(blocks), dim3(bs), 0, nullptr,
                        static_cast<const int32_t *>(g->rp), g->col, g->head, g->n);
+  hipLaunchKernelGGL(k_build_headc, dim3(blocks), dim3(bs), 0, nullptr, g->head, g->iso, g->hrank, g->headc,
+                     g->words);
   BFS_HIP(hipGetLastError());
   BFS_HIP(hipDeviceSynchronize());
   return BFS_OK;
