@@ -450,6 +450,8 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
 // degrees are three rounds of independent requests instead of three per
 // neighbour), then the rest of the row in lock-step with the wavefront.
 // All lanes of the wavefront call it together.
+constexpr int kTdUnroll = 2;  // neighbours per lane per step in the wavefront / workgroup roles
+
 // Claims K neighbours x[k] (-1: none) of frontier vertex u[k] per lane
 // together: their visited words, the claims and the new vertices' degrees
 // are three rounds of K independent requests instead of three per
@@ -458,17 +460,17 @@ template <int K, class RowT>
 __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
                                                const int32_t (&x)[K], const int32_t (&u)[K],
                                                unsigned long long &nfound, unsigned long long &dfound) {
-  uint64_t w[K];
+  // (32-bit halves of the visited words: half the registers of 64-bit ones)
+  uint32_t *vis32 = reinterpret_cast<uint32_t *>(G.vis);
+  uint32_t w[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? G.vis[x[k] >> 6] : ~0ull;
+  for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? vis32[x[k] >> 5] : ~0u;
   bool win[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint64_t bit = x[k] >= 0 ? 1ull << (x[k] & 63) : 0ull;
+    const uint32_t bit = x[k] >= 0 ? 1u << (x[k] & 31) : 0u;
     win[k] = false;
-    if (x[k] >= 0 && !(w[k] & bit))
-      win[k] = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (x[k] >> 6)), (unsigned long long)bit) &
-                 bit);
+    if (x[k] >= 0 && !(w[k] & bit)) win[k] = !(atomicOr(vis32 + (x[k] >> 5), bit) & bit);
   }
   int32_t dv[K];
 #pragma unroll
@@ -503,7 +505,6 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
   }
 }
 
-constexpr int kTdUnroll = 2;  // neighbours per lane per step in the wavefront / workgroup roles
 
 // One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
 //   [0, nb_small)                 thread per vertex of degree <= t1;
@@ -716,6 +717,23 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   }
   uint32_t *arrive = reinterpret_cast<uint32_t *>(G.partials + kArriveOffset);
   constexpr int kLineU32 = 2 * kLineU64;
+  if (nactive == 1) {  // the only workgroup of the level: reduce in LDS and decide
+    __shared__ unsigned long long one[K][16];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const unsigned long long sum = wave_sum(v[k]);
+      if (lane_id() == 0) one[k][w] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot[kPartials] = {0, 0, 0, 0};
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot[k] += one[k][i];
+      decide_apply(G.ctl, G.recs, tot);
+    }
+    return;
+  }
   if (nactive <= (unsigned)kFenceDecideBlocks) {
     block_partials<K>(G, v, rank);  // written by wave 0, whose fence below releases them
     __shared__ int last;
