@@ -132,10 +132,80 @@ def bench_batched(bfs, torch, reps=3):
         batch.append((time.perf_counter() - t0) * 1e3)
     m = sum(edges.values())
     tb, tp = statistics.median(batch), statistics.median(plain)
+    del out8
+    visited = ablation(bfs, torch, gh, sources[:4])
     gh.close()
     return {"workload": "rmat22_ef16_64src", "n": g.n, "nnz": g.nnz, "batch_ms": round(tb, 3),
             "plain_64_ms": round(tp, 3), "batch_gteps": round(m / tb / 1e6, 3),
-            "plain_gteps": round(m / tp / 1e6, 3), "speedup": round(tp / tb, 3)}
+            "plain_gteps": round(m / tp / 1e6, 3), "speedup": round(tp / tb, 3),
+            "visited_test_ablation_4src_td_only": visited}
+
+
+POLICY_NAMES = {1: "alpha_beta (BFS-Hybrid dagger)", 2: "frontier_5pct (BFS-Hybrid)", 3: "td_only"}
+
+
+def policy_study(bfs, torch, gh, sources, reps=2):
+    """Section 2's two switching rules and the top-down-only schedule that
+    Section 3's classifier picks for sparse graphs, each on the same sources
+    (captured loop): harmonic-mean GTEPS and the direction schedules."""
+    params = bfs.bfs_get_params(gh)
+    dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
+    out = {}
+    for pol, name in POLICY_NAMES.items():
+        bfs.bfs_set_params(gh, policy=pol)
+        bfs.bfs_run(gh, int(sources[0]), dist)
+        per, sched = {}, {}
+        for _ in range(reps):
+            for s in sources:
+                bfs.bfs_run(gh, int(s), dist)
+                run, lvs = bfs.bfs_get_run_stats(gh)
+                per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
+                key = "".join("TB"[lv["direction"]] for lv in lvs)
+                key = key if len(key) <= 16 else f"{key[:8]}..({len(key)} levels)"
+                sched[key] = sched.get(key, 0) + 1
+        teps = [e / statistics.median(t) for e, t in per.values()]
+        out[name] = {"gteps_hm": round(len(teps) / sum(1.0 / t for t in teps) / 1e9, 3),
+                     "schedules": dict(sorted(sched.items(), key=lambda kv: -kv[1])[:4])}
+    bfs.bfs_set_params(gh, **params)
+    return out
+
+
+TD_VISITED = {0: "VisitedBitmap (bitmap, atomic OR)", 1: "Conventional (CAS on dist)",
+              2: "NonAtomic (plain dist test and store)",
+              3: "NonAtomic, duplicate copies culled at expansion"}
+
+
+def ablation(bfs, torch, gh, sources, reps=1):
+    """Section 2's visited tests as top-down-only searches on the same
+    sources (captured loop): harmonic-mean GTEPS, and for the non-atomic
+    test the share of duplicate frontier entries it created (frontier
+    entries over the bitmap run's, minus one)."""
+    params = bfs.bfs_get_params(gh)
+    dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
+    out, nf_base = {}, None
+    for mode, name in TD_VISITED.items():
+        bfs.bfs_set_params(gh, policy=bfs.BFS_POLICY_TD_ONLY, td_visited=mode)
+        per, nf = {}, 0
+        try:
+            bfs.bfs_run(gh, int(sources[0]), dist)
+            for _ in range(reps):
+                for s in sources:
+                    bfs.bfs_run(gh, int(s), dist)
+                    run, lvs = bfs.bfs_get_run_stats(gh)
+                    per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
+                    nf += sum(lv["frontier"] for lv in lvs)
+        except bfs.BfsError as e:  # e.g. duplicates outgrowing the queues
+            out[name] = {"error": str(e)}
+            continue
+        # edges: the component's, from the exact (bitmap) run of each source
+        if nf_base is None:
+            edges = {s: e for s, (e, _) in per.items()}
+            nf_base = nf
+        teps = [edges[s] / statistics.median(t) for s, (_, t) in per.items()]
+        out[name] = {"gteps_hm": round(len(teps) / sum(1.0 / t for t in teps) / 1e9, 3),
+                     "duplicate_frontier_share": round(nf / nf_base - 1.0, 5)}
+    bfs.bfs_set_params(gh, **params)
+    return out
 
 
 def bench_mesh(bfs, torch, reps=2):
@@ -154,12 +224,15 @@ def bench_mesh(bfs, torch, reps=2):
             per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
             levels.append(run["levels"])
     teps = [e / statistics.median(t) for e, t in per.values()]
+    policies = policy_study(bfs, torch, gh, sources[:4], reps=1)
+    visited = ablation(bfs, torch, gh, sources[:4])
     gh.close()
     hm = len(teps) / sum(1.0 / t for t in teps) / 1e9
     mean_ms = statistics.mean(statistics.median(t) for _, t in per.values()) * 1e3
     return {"workload": "grid4096_p0.1_16src", "n": g.n, "nnz": g.nnz, "gteps_hm": round(hm, 4),
             "ms_per_bfs": round(mean_ms, 3), "levels_mean": round(statistics.mean(levels), 1),
-            "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2)}
+            "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2),
+            "policy_study_4src": policies, "visited_test_ablation_4src": visited}
 
 
 # Serving pool: RMAT scales 14-22 and 23, perturbed lattices without
@@ -370,6 +443,7 @@ def main():
     torch.cuda.synchronize()
     gteps_host_loop = hm_gteps(inst, "host_ms")
     bfs.bfs_set_params(gh, **params)
+    policies = None if args.no_extras else policy_study(bfs, torch, gh, sources[:16])
 
     # level breakdown and the bottom-up kernel's roofline
     runs = len(inst)
@@ -429,6 +503,7 @@ def main():
         "td_ms_per_bfs": round(td_ms, 4),
         "bu_ms_per_bfs": round(bu_ms, 4),
         "direction_schedules": schedules,
+        "policy_study_16src": policies,
     }
     gh.close()
     del dist, parent

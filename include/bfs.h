@@ -70,6 +70,34 @@ typedef enum bfs_policy {
   BFS_POLICY_TD_ONLY = 3
 } bfs_policy;
 
+/* Visited test of top-down levels (bfs_params.td_visited), Section 2:
+   BITMAP     - BFS-VisitedBitmap: one bit per vertex, claimed with an atomic OR;
+   DIST_CAS   - BFS-Conventional: the distance itself, claimed with a
+                compare-and-swap from -1 (no bitmap);
+   DIST_PLAIN - BFS-NonAtomic: a plain test of the distance and a plain store
+                of the (agreed) new value; racing discoverers may each append
+                the vertex, so frontiers can hold duplicates (counted in the
+                level statistics), and every copy is expanded at the next
+                level, where its discoveries can be duplicated in turn.  The
+                queues then hold n + nnz entries per set; a level that
+                appends more makes bfs_run fail with BFS_ERR_OUT_OF_MEMORY
+                (entries past the end are dropped, never written).  On a
+                wide-front lattice the copies multiply along the shortest
+                paths, so this mode is expected to fail there;
+   DIST_PLAIN_CULL - the same plain test and store, and duplicates still
+                enter the queue, but each appender also stores the queue
+                position it wrote into a per-vertex slot (plain store, last
+                writer wins) and only the copy at that position is expanded,
+                so duplicate work ends after one level (an n-entry array more).
+                Large-degree vertices (one entry per t2-edge chunk) are not
+                culled. */
+typedef enum bfs_td_visited {
+  BFS_TD_VISITED_BITMAP = 0,
+  BFS_TD_DIST_CAS = 1,
+  BFS_TD_DIST_PLAIN = 2,
+  BFS_TD_DIST_PLAIN_CULL = 3
+} bfs_td_visited;
+
 /* Level-loop drivers (bfs_params.loop). */
 typedef enum bfs_loop {
   BFS_LOOP_AUTO = 0,  /* GRAPH */
@@ -111,7 +139,10 @@ typedef struct bfs_params {
                                  wavefront up to 1024 workgroups; at most 1024) */
   int32_t queue_ahead;        /* QUEUED loop: levels kept enqueued ahead of the device (default 2,
                                  at most 64) */
-  int32_t reserved[1];
+  int32_t td_visited;         /* how a top-down level tells visited vertices (paper Section 2):
+                                 BFS_TD_VISITED_BITMAP (default) or, for the paper's ablation and
+                                 only with the top-down-only policy, BFS_TD_DIST_CAS,
+                                 BFS_TD_DIST_PLAIN or BFS_TD_DIST_PLAIN_CULL */
 } bfs_params;
 
 /* One record per executed level of the last bfs_run on a graph. */

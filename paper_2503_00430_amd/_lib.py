@@ -13,6 +13,11 @@ _lock = threading.Lock()
 _lib = None
 
 BFS_OK = 0
+BFS_ERR_INVALID_ARG = 1
+BFS_ERR_OUT_OF_MEMORY = 2
+BFS_ERR_DEVICE = 3
+BFS_ERR_BUSY = 4
+BFS_ERR_NOT_READY = 5
 BFS_INPUT_DEVICE = 0x1
 BFS_VALIDATE = 0x2
 BFS_VALIDATE_SYMMETRY = 0x4
@@ -29,6 +34,10 @@ BFS_LOOP_HOST = 1
 BFS_LOOP_GRAPH = 2
 BFS_LOOP_PERSISTENT = 3
 BFS_LOOP_QUEUED = 4
+BFS_TD_VISITED_BITMAP = 0
+BFS_TD_DIST_CAS = 1
+BFS_TD_DIST_PLAIN = 2
+BFS_TD_DIST_PLAIN_CULL = 3
 
 BFS_REQ_QUEUED = 0
 BFS_REQ_RUNNING = 1
@@ -43,7 +52,7 @@ class bfs_params(ctypes.Structure):
     _fields_ = [(name, _i32) for name in (
         "policy", "alpha", "beta", "td_wave_degree", "td_block_degree", "bu_wave_degree",
         "block_size", "loop", "graph_chunk_levels", "collect_timing", "msbfs_block_size",
-        "msbfs_bu_percent", "graph_td_blocks", "bu_blocks", "queue_ahead")] + [("reserved", _i32 * 1)]
+        "msbfs_bu_percent", "graph_td_blocks", "bu_blocks", "queue_ahead", "td_visited")]
 
 
 class bfs_level_stats(ctypes.Structure):

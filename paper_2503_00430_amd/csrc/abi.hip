@@ -55,32 +55,67 @@ static hipError_t dev_alloc(T *&p, size_t count, int64_t &acct) {
   return e;
 }
 
-// Large-degree queue capacity: every large vertex has degree > t2, so there
-// are at most nnz / t2 of them, and they hold at most nnz / t2 + count
-// chunks of t2 edges.
+// Queue capacities.  With a test-and-set visited check (bitmap or
+// compare-and-swap) every vertex enters the frontier once, so a set's small
+// and medium queues hold at most n entries; every large vertex has degree
+// > t2, so there are at most nnz / t2 of them, holding at most
+// nnz / t2 + count chunks of t2 edges.  The visited test of plain loads and
+// stores (Section 2, BFS-NonAtomic) lets racing discoverers append a vertex
+// again, up to once per examined edge, so its queues are sized for the
+// edges as well; a level that still outgrows them is stopped and reported.
+static int64_t queue_capacity(const bfs_graph *g) {
+  int64_t cap = g->n;
+  if (g->params.td_visited >= BFS_TD_DIST_PLAIN) cap += g->nnz;
+  return std::min<int64_t>(cap, INT32_MAX);
+}
+
 static int64_t large_capacity(const bfs_graph *g) {
   int64_t t2 = std::max<int64_t>(g->params.td_block_degree, 1);
-  return 2 * (g->nnz / t2) + 2;
+  int64_t cap = 2 * (g->nnz / t2) + 2;
+  if (g->params.td_visited >= BFS_TD_DIST_PLAIN) cap *= 8;
+  return std::min<int64_t>(cap, INT32_MAX);
+}
+
+template <class T>
+static int grow_queues(bfs_graph *g, T *(&q)[2], int64_t &have, int64_t cap, const char *what) {
+  if (cap <= have) return BFS_OK;
+  for (int s = 0; s < 2; ++s) {
+    if (q[s]) {
+      g->device_bytes -= have * (int64_t)sizeof(T);
+      void *p = q[s];
+      free_dev(p);
+      q[s] = nullptr;
+    }
+  }
+  have = 0;
+  for (int s = 0; s < 2; ++s) {
+    if (dev_alloc(q[s], cap, g->device_bytes) != hipSuccess) {
+      if (s == 1) {  // keep the pair consistent: release the first of the two
+        g->device_bytes -= cap * (int64_t)sizeof(T);
+        void *p = q[0];
+        free_dev(p);
+        q[0] = nullptr;
+      }
+      return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate %lld %s queue entries", (long long)cap, what);
+    }
+  }
+  have = cap;
+  return BFS_OK;
 }
 
 int alloc_single_scratch(bfs_graph *g) {
-  int64_t cap = large_capacity(g);
-  if (cap <= g->ql_cap) return BFS_OK;
-  for (int s = 0; s < 2; ++s) {
-    if (g->ql[s]) {
-      g->device_bytes -= g->ql_cap * (int64_t)sizeof(uint64_t);
-      void *p = g->ql[s];
-      free_dev(p);
-      g->ql[s] = nullptr;
-    }
-  }
-  g->ql_cap = 0;
-  for (int s = 0; s < 2; ++s) {
-    if (dev_alloc(g->ql[s], cap, g->device_bytes) != hipSuccess)
-      return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate %lld large-vertex queue entries",
-                  (long long)cap);
-  }
-  g->ql_cap = cap;
+  const int64_t qcap = queue_capacity(g);
+  int64_t small_have = g->q_cap, medium_have = g->q_cap;
+  int rc = grow_queues(g, g->qs, small_have, qcap, "small-vertex");
+  if (!rc) rc = grow_queues(g, g->qm, medium_have, qcap, "medium-vertex");
+  // both kinds now hold at least the smaller of the two counts
+  g->q_cap = std::min(small_have, medium_have);
+  if (rc) return rc;
+  rc = grow_queues(g, g->ql, g->ql_cap, large_capacity(g), "large-vertex");
+  if (rc) return rc;
+  if (g->params.td_visited == BFS_TD_DIST_PLAIN_CULL && !g->slot &&
+      dev_alloc(g->slot, g->n, g->device_bytes) != hipSuccess)
+    return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate the %lld-entry queue-slot array", (long long)g->n);
   return BFS_OK;
 }
 
@@ -97,7 +132,7 @@ static void destroy(bfs_graph *g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   release_graph_exec(g);
   void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->headc, g->hrank, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
-                  g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->ctl, g->recs, g->partials,
+                  g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->slot, g->ctl, g->recs, g->partials,
                   g->ms.seen, g->ms.front, g->ms.next, g->ms.counters};
   for (void *p : ptrs) free_dev(p);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
@@ -151,6 +186,7 @@ static bfs_params default_params() {
   p.msbfs_bu_percent = 5;
   p.graph_td_blocks = 128;
   p.queue_ahead = 2;
+  p.td_visited = BFS_TD_VISITED_BITMAP;
   return p;
 }
 
@@ -171,6 +207,8 @@ static int check_params(const bfs_params &p) {
     return fail(BFS_ERR_INVALID_ARG, "graph_chunk_levels must be in [1, 4096]");
   if (p.graph_td_blocks < 1 || p.graph_td_blocks > 512)
     return fail(BFS_ERR_INVALID_ARG, "graph_td_blocks must be in [1, 512]");
+  if (p.td_visited < BFS_TD_VISITED_BITMAP || p.td_visited > BFS_TD_DIST_PLAIN_CULL)
+    return fail(BFS_ERR_INVALID_ARG, "unknown td_visited %d", p.td_visited);
   if (p.queue_ahead < 1 || p.queue_ahead > 64)
     return fail(BFS_ERR_INVALID_ARG, "queue_ahead must be in [1, 64]");
   if (p.bu_blocks < 0 || p.bu_blocks > kMaxBlocks)
@@ -304,10 +342,6 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   ALLOC(g->vis, g->words);
   ALLOC(g->bm[0], g->words);
   ALLOC(g->bm[1], g->words);
-  for (int s = 0; s < 2; ++s) {
-    ALLOC(g->qs[s], n);
-    ALLOC(g->qm[s], n);
-  }
   ALLOC(g->ctl, 1);
   ALLOC(g->partials, kPartialsAlloc);
   g->rec_cap = 1 << 16;

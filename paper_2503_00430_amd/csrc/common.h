@@ -46,7 +46,8 @@ struct alignas(256) Ctl {
   int32_t alpha, beta;
   int32_t rec_cap;  // capacity of the LevelRec array
   int32_t levels_done;
-  int32_t pad0;
+  int32_t overflow; // nonzero: a level appended more entries than a queue holds
+                    // (entries past the end were dropped; the search stops)
   int64_t n;        // vertex count
   int64_t n_f;      // size of the current frontier
   int64_t m_f;      // sum of degrees over the current frontier
@@ -54,7 +55,7 @@ struct alignas(256) Ctl {
   int64_t sum_mf;   // sum of m_f over all levels so far (= 2 * TEPS edge count)
   int64_t reached;  // vertices visited so far
   unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
-  unsigned int pad1[2];
+  unsigned int qcap[2];     // capacity of each small/medium queue, of each large queue
   int32_t *dist;    // outputs of the current search
   int32_t *parent;
   Ctl *mirror;      // host-mapped copy the decide step publishes after every level
@@ -101,6 +102,10 @@ struct DevG {
   int64_t n;
   int64_t words;        // 64-bit words per bitmap
   int32_t t1, t2, tbu;  // degree thresholds (td_wave_degree, td_block_degree, bu_wave_degree)
+  int32_t td_visited;   // bfs_td_visited of the top-down claims
+  uint32_t qcap, lcap;  // entries each small/medium queue and each large queue holds
+  int32_t *slot;        // BFS_TD_DIST_PLAIN_CULL only (else null): per vertex, the
+                        // queue position its last appender wrote
 };
 
 // Scratch of the batched (multi-source) search, allocated on first use.
@@ -129,6 +134,8 @@ struct bfs_graph {
   int32_t *qm[2] = {nullptr, nullptr};
   uint64_t *ql[2] = {nullptr, nullptr};
   int64_t ql_cap = 0;
+  int64_t q_cap = 0;  // entries of each small/medium queue
+  int32_t *slot = nullptr;  // n entries, allocated for BFS_TD_DIST_PLAIN_CULL
   bfsmi::Ctl *ctl = nullptr;
   bfsmi::Ctl *ctl_host = nullptr;  // pinned, coherent, device-mapped mirror of ctl
   bfsmi::Ctl *ctl_host_dev = nullptr;  // its device-side address

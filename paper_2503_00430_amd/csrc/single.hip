@@ -150,8 +150,10 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       const unsigned slot = base + lanes_below(m);
       if (slot < cap)
         (bb == kSmall ? S.small : S.medium)[slot] = v;
-      else
+      else if (gbase + (slot - first_over) < G.qcap) {  // past the end: dropped, the decide step stops
         global_queue(G, qn, bb)[gbase + (slot - first_over)] = v;
+        if (G.slot) G.slot[v] = (int32_t)(gbase + (slot - first_over));
+      }
     }
   }
   if (b == kLarge) {  // rare: one entry per t2-edge chunk
@@ -167,7 +169,7 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       const uint64_t e = ((uint64_t)k << 32) | (uint32_t)v;
       if (slot < cap)
         S.large[slot] = e;
-      else
+      else if (gbase + (slot - first_over) < G.lcap)
         gq[gbase + (slot - first_over)] = e;
     }
   }
@@ -195,9 +197,20 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   int32_t *qs = global_queue(G, qn, kSmall);
   int32_t *qm = global_queue(G, qn, kMedium);
   uint64_t *ql = qn ? G.ql[1] : G.ql[0];
-  for (unsigned i = threadIdx.x; i < count[kSmall]; i += blockDim.x) qs[gbase[kSmall] + i] = S.small[i];
-  for (unsigned i = threadIdx.x; i < count[kMedium]; i += blockDim.x) qm[gbase[kMedium] + i] = S.medium[i];
-  for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x) ql[gbase[kLarge] + i] = S.large[i];
+  // entries that would land past a queue's end are dropped (the counts still
+  // grow, and the decide step turns that into an error)
+  for (unsigned i = threadIdx.x; i < count[kSmall]; i += blockDim.x)
+    if (gbase[kSmall] + i < G.qcap) {
+      qs[gbase[kSmall] + i] = S.small[i];
+      if (G.slot) G.slot[S.small[i]] = (int32_t)(gbase[kSmall] + i);
+    }
+  for (unsigned i = threadIdx.x; i < count[kMedium]; i += blockDim.x)
+    if (gbase[kMedium] + i < G.qcap) {
+      qm[gbase[kMedium] + i] = S.medium[i];
+      if (G.slot) G.slot[S.medium[i]] = (int32_t)(gbase[kMedium] + i);
+    }
+  for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x)
+    if (gbase[kLarge] + i < G.lcap) ql[gbase[kLarge] + i] = S.large[i];
   __syncthreads();
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -260,6 +273,9 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->beta = beta;
     c->rec_cap = rec_cap;
     c->levels_done = 0;
+    c->overflow = 0;
+    c->qcap[0] = G.qcap;
+    c->qcap[1] = G.lcap;
     c->n = G.n;
     c->n_f = 1;
     c->m_f = deg;
@@ -275,6 +291,7 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
       c->qcnt[0][kLarge] = nch;
     } else {
       (b == kSmall ? G.qs[0] : G.qm[0])[0] = s;
+      if (G.slot) G.slot[s] = 0;
       c->qcnt[0][b] = 1;
     }
     c->dist = dist;
@@ -315,6 +332,17 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     // becomes the target of the following top-down level
     for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
     c->qcur ^= 1;
+    // with the visited test of plain loads and stores a vertex can be
+    // appended once per racing discoverer; a set that outgrew its queues
+    // lost entries, so the search ends here and the host reports it
+    const unsigned *q = c->qcnt[c->qcur];
+    if (q[kSmall] > c->qcap[0] || q[kMedium] > c->qcap[0] || q[kLarge] > c->qcap[1]) {
+      c->overflow = 1;
+      c->done = 1;
+      c->conv = kConvNone;
+      publish(c);
+      return;
+    }
   } else {
     c->bcur ^= 1;
   }
@@ -402,9 +430,15 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
                                          int32_t v, unsigned long long &nfound, unsigned long long &dfound) {
   bool win = false;
   int64_t deg = 0;
-  if (has && claim(G.vis, v)) {
+  bool claimed = false;
+  if (has) {
+    if (G.td_visited == BFS_TD_VISITED_BITMAP) claimed = claim(G.vis, v);
+    else if (G.td_visited == BFS_TD_DIST_CAS) claimed = atomicCAS(dist + v, -1, level + 1) == -1;
+    else claimed = dist[v] < 0;  // plain test: racing discoverers may all pass
+  }
+  if (claimed) {
     win = true;
-    dist[v] = level + 1;  // plain store: the claim made this lane the only writer
+    dist[v] = level + 1;  // plain store: every writer of v stores this same value
     if (parent) parent[v] = u;
     fbm_set(fbm, v);
     deg = G.head[v].x;
@@ -460,17 +494,28 @@ template <int K, class RowT>
 __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage &S, const TdLevel &T, int qn,
                                                const int32_t (&x)[K], const int32_t (&u)[K],
                                                unsigned long long &nfound, unsigned long long &dfound) {
-  // (32-bit halves of the visited words: half the registers of 64-bit ones)
-  uint32_t *vis32 = reinterpret_cast<uint32_t *>(G.vis);
-  uint32_t w[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? vis32[x[k] >> 5] : ~0u;
   bool win[K];
+  if (G.td_visited == BFS_TD_VISITED_BITMAP) {
+    // (32-bit halves of the visited words: half the registers of 64-bit ones)
+    uint32_t *vis32 = reinterpret_cast<uint32_t *>(G.vis);
+    uint32_t w[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t bit = x[k] >= 0 ? 1u << (x[k] & 31) : 0u;
-    win[k] = false;
-    if (x[k] >= 0 && !(w[k] & bit)) win[k] = !(atomicOr(vis32 + (x[k] >> 5), bit) & bit);
+    for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? vis32[x[k] >> 5] : ~0u;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t bit = x[k] >= 0 ? 1u << (x[k] & 31) : 0u;
+      win[k] = false;
+      if (x[k] >= 0 && !(w[k] & bit)) win[k] = !(atomicOr(vis32 + (x[k] >> 5), bit) & bit);
+    }
+  } else if (G.td_visited == BFS_TD_DIST_CAS) {  // Section 2, BFS-Conventional
+#pragma unroll
+    for (int k = 0; k < K; ++k) win[k] = x[k] >= 0 && atomicCAS(T.dist + x[k], -1, T.level + 1) == -1;
+  } else {  // Section 2, BFS-NonAtomic (either form): a plain test, duplicates allowed
+    int32_t d[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) d[k] = x[k] >= 0 ? T.dist[x[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) win[k] = x[k] >= 0 && d[k] < 0;
   }
   int32_t dv[K];
 #pragma unroll
@@ -478,7 +523,7 @@ __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if (win[k]) {
-      T.dist[x[k]] = T.level + 1;  // plain store: the claim made this lane the only writer
+      T.dist[x[k]] = T.level + 1;  // plain store: every writer of x[k] stores this same value
       if (T.parent) T.parent[x[k]] = u[k];
       fbm_set(T.fbm, x[k]);
       nfound += 1;
@@ -530,8 +575,9 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     const int64_t step = (int64_t)nb_small * blockDim.x;
     for (int64_t round = (int64_t)blk * blockDim.x; round < cnt; round += step) {
       const int64_t i = round + wib * kWave + lane;
-      const bool act = i < cnt;
+      bool act = i < cnt;
       const int32_t u = act ? q[i] : 0;
+      if (act && G.slot) act = G.slot[u] == (int32_t)i;  // culled duplicate: expand only the recorded copy
       int4 h = make_int4(0, -1, -1, -1);
       int64_t row0 = 0;
       if (act) {
@@ -548,8 +594,8 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     const int64_t waves = (int64_t)nb_med * wpb;
     for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < cnt; round += waves) {
       const int64_t i = round + wib;
-      if (i < cnt) {  // uniform within the wavefront
-        const int32_t u = q[i];
+      const int32_t u = i < cnt ? q[i] : -1;  // uniform within the wavefront
+      if (u >= 0 && (!G.slot || G.slot[u] == (int32_t)i)) {  // (culled duplicates skip)
         if (lane == 0) fbm_clear(T.fbm, u);
         const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
         for (int64_t b = beg; b < end; b += (int64_t)kWave * kTdUnroll) {
@@ -1227,6 +1273,10 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.t1 = g->params.td_wave_degree;
   G.t2 = g->params.td_block_degree;
   G.tbu = g->params.bu_wave_degree;
+  G.td_visited = g->params.td_visited;
+  G.qcap = (uint32_t)g->q_cap;
+  G.lcap = (uint32_t)g->ql_cap;
+  G.slot = g->params.td_visited == BFS_TD_DIST_PLAIN_CULL ? g->slot : nullptr;
   return G;
 }
 
@@ -1536,6 +1586,11 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   const DevG<RowT> G = make_devg<RowT>(g);
   hipStream_t st = g->stream;
   const int policy = resolved_policy(g);
+  if (g->params.td_visited != BFS_TD_VISITED_BITMAP && policy != BFS_POLICY_TD_ONLY)
+    return fail(BFS_ERR_INVALID_ARG, "td_visited other than the bitmap needs the top-down-only policy");
+  for (int q = 0; q < 2; ++q)
+    if (!g->qs[q] || !g->qm[q] || !g->ql[q] || g->q_cap < 1 || g->ql_cap < 1)
+      return fail(BFS_ERR_OUT_OF_MEMORY, "the frontier queues are not allocated (a failed bfs_set_params?)");
   int loop = g->params.loop;
   if (loop == BFS_LOOP_AUTO) loop = BFS_LOOP_GRAPH;
   if (loop == BFS_LOOP_PERSISTENT && policy != BFS_POLICY_TD_ONLY) loop = BFS_LOOP_HOST;
@@ -1591,6 +1646,11 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   L.host_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   L.loop = loop;
   L.policy = policy;
+  if (h.overflow)
+    return fail(BFS_ERR_OUT_OF_MEMORY,
+                "level %d appended more frontier entries than the queues hold (%lld per small/medium "
+                "queue, %lld per large queue); distances past that level are incomplete",
+                h.levels_done - 1, (long long)g->q_cap, (long long)g->ql_cap);
   return BFS_OK;
 }
 

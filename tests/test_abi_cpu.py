@@ -107,4 +107,4 @@ def test_loop_param_defaults(lib):
     """Defaults of the queued-loop lookahead and the bottom-up grid."""
     import paper_2503_00430_amd._lib as L
     d = L.bfs_default_params()
-    assert d["queue_ahead"] == 2 and d["bu_blocks"] == 0
+    assert d["queue_ahead"] == 2 and d["bu_blocks"] == 0 and d["td_visited"] == 0

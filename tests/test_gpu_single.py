@@ -331,3 +331,89 @@ def test_rmat20_repeated_full_parity(rmat20, rmat20_hub_first, policy, sort):
         for rep in range(3):
             check_single(g, gh, s, ref=ref, full_validate=(rep == 0), scan_order=order)
     gh.close()
+
+
+@pytest.mark.parametrize("loop", [1, 2, 3, 4])
+def test_td_visited_dist_cas(rmat16, loop):
+    """The paper's BFS-Conventional visited test (compare-and-swap on the
+    distance, no bitmap): distances, parents and every level statistic as
+    the oracle's top-down-only replay."""
+    bfs = library()
+    say("td_visited dist_cas, loop", loop)
+    for g in (rmat16, graphgen.grid(256), graphs.path(500)[0]):
+        gh = upload(g)
+        bfs.bfs_set_params(gh, policy=3, loop=loop, td_visited=bfs.BFS_TD_DIST_CAS)
+        for s in graphgen.sources(g, 3, seed=7):
+            check_single(g, gh, s)
+        gh.close()
+
+
+def _check_plain(bfs, g, gh, s, overflow_ok=False):
+    """Distances of a plain-visited-test search bit-exact, parents valid,
+    per-level frontiers at least the oracle's.  With `overflow_ok` the
+    search may instead stop with the documented queue-overflow error."""
+    try:
+        d, p = gpu_bfs(gh, s)
+    except bfs.BfsError as e:
+        assert overflow_ok and e.code == bfs.BFS_ERR_OUT_OF_MEMORY, e
+        assert "appended more frontier entries than the queues hold" in str(e)
+        return False
+    od = oracle.bfs(g, s, want_parent=False)[0]
+    assert np.array_equal(d, od)
+    assert oracle.validate(g, s, d, p, check_component=True) == []
+    run, levels = bfs.bfs_get_run_stats(gh)
+    st = oracle.level_stats(g, od)
+    assert run["levels"] == st["depth"] and run["reached"] >= st["reached"]
+    nf = np.array([lv["frontier"] for lv in levels])
+    assert nf[0] == 1 and (nf >= st["h"]).all()
+    assert all(lv["direction"] == 0 for lv in levels)
+    return True
+
+
+@pytest.mark.parametrize("loop", [1, 2, 3, 4])
+def test_td_visited_dist_plain(rmat16, loop):
+    """The paper's BFS-NonAtomic visited test (plain test and store of the
+    distance): distances bit-exact and parents valid; racing discoverers may
+    append a vertex more than once, so each level's frontier is at least the
+    oracle's and the level count is the same.  Every copy is expanded, so on
+    the lattice the copies can multiply along shortest paths until the
+    queues are full: there the search must either finish exact or stop with
+    the overflow error (never write past a queue)."""
+    bfs = library()
+    say("td_visited dist_plain, loop", loop)
+    for g, lattice in ((rmat16, False), (graphgen.grid(256), True), (graphs.path(500)[0], False)):
+        gh = upload(g)
+        bfs.bfs_set_params(gh, policy=3, loop=loop, td_visited=bfs.BFS_TD_DIST_PLAIN)
+        for s in graphgen.sources(g, 3, seed=7):
+            _check_plain(bfs, g, gh, s, overflow_ok=lattice)
+        # the handle stays usable after an overflow
+        bfs.bfs_set_params(gh, td_visited=bfs.BFS_TD_VISITED_BITMAP)
+        check_single(g, gh, int(graphgen.sources(g, 1, seed=8)[0]))
+        gh.close()
+
+
+@pytest.mark.parametrize("loop", [1, 2, 3, 4])
+def test_td_visited_dist_plain_cull(rmat16, loop):
+    """The plain visited test with duplicate copies culled at expansion
+    (only the copy whose position the last appender recorded expands):
+    exact distances on every graph, the lattice included."""
+    bfs = library()
+    say("td_visited dist_plain_cull, loop", loop)
+    for g in (rmat16, graphgen.grid(256), graphs.path(500)[0], graphs.deferred_rows()[0]):
+        gh = upload(g)
+        bfs.bfs_set_params(gh, policy=3, loop=loop, td_visited=bfs.BFS_TD_DIST_PLAIN_CULL)
+        for s in graphgen.sources(g, 3, seed=7):
+            assert _check_plain(bfs, g, gh, s)
+        gh.close()
+
+
+def test_td_visited_needs_td_only(rmat16):
+    bfs = library()
+    say("td_visited needs top-down only")
+    gh = upload(rmat16)
+    bfs.bfs_set_params(gh, policy=1, td_visited=bfs.BFS_TD_DIST_CAS)
+    with pytest.raises(bfs.BfsError):
+        gpu_bfs(gh, 0)
+    bfs.bfs_set_params(gh, td_visited=bfs.BFS_TD_VISITED_BITMAP)
+    check_single(rmat16, gh, int(graphgen.sources(rmat16, 1)[0]))
+    gh.close()
