@@ -184,8 +184,12 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   __shared__ unsigned gbase[3], count[3];
   __syncthreads();
   const unsigned bs = blockDim.x;
-  if (only_if_half_full && S.cnt[kSmall] < 4 * bs && S.cnt[kMedium] < bs && S.cnt[kLarge] < bs / 2)
-    return;  // uniform: every thread reads the same counts after the barrier
+  if (only_if_half_full) {
+    const bool skip = S.cnt[kSmall] < 4 * bs && S.cnt[kMedium] < bs && S.cnt[kLarge] < bs / 2;
+    // every thread has read the counts before any wavefront can stage again
+    __syncthreads();
+    if (skip) return;  // uniform: the same counts were read by every thread
+  }
   if (threadIdx.x < 3) {
     const unsigned b = threadIdx.x;
     const unsigned cap = b == kSmall ? 8 * bs : (b == kMedium ? 2 * bs : bs);  // as in stage_open
@@ -310,6 +314,11 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
 __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&tot)[kPartials]) {
   const int32_t L = c->level;
   const int32_t cur = c->dir;
+  // The level number changes first, and reaches the cache before any other
+  // field changes: a workgroup of this level's launch that starts only now
+  // reads the fields, then the number, and leaves when the number moved on.
+  c->level = L + 1;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   const int64_t found = (int64_t)tot[0];
   const int64_t fdeg = (int64_t)tot[1];
   if (L < c->rec_cap) {
@@ -372,7 +381,6 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   c->m_f = fdeg;
   c->m_u = m_u;
   c->dir = nxt;
-  c->level = L + 1;
   if (c->pub_mode == kPubEvery) publish(c);
 }
 
@@ -460,6 +468,7 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
 struct TdLevel {
   int32_t qcur, level;
   int64_t cnt[3];
+  int64_t m_f;         // degree sum of the frontier (steers the medium-row split)
   int32_t *dist, *parent;
   uint64_t *fbm;       // current frontier bitmap (hybrid searches), else null
   bool from_bitmap;    // the frontier is the bitmap of a bottom-up level
@@ -471,6 +480,7 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
   t.qcur = c->qcur;
   t.level = c->level;
   for (int b = 0; b < 3; ++b) t.cnt[b] = c->qcnt[t.qcur][b];
+  t.m_f = c->m_f;
   t.dist = c->dist;
   t.parent = c->parent;
   t.fbm = c->policy != BFS_POLICY_TD_ONLY ? (c->bcur ? G.bm[1] : G.bm[0]) : nullptr;
@@ -559,6 +569,19 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
 //                                 vertex.
 // Ends with the staged queue entries flushed and the workgroup's counts in
 // `counts`.  All threads of the workgroup call it.
+// Wavefronts per medium vertex: as many as the role has per queued vertex,
+// at most one per kWave * kTdUnroll edges of the longest medium row (t2).
+// A level whose whole frontier has fewer than kSplitMinEdges edges keeps one
+// wavefront per vertex: there the split would only wake more workgroups
+// (and take the level off the single-workgroup decide).
+constexpr int64_t kSplitMinEdges = 1024;
+__host__ __device__ inline int64_t medium_split(int64_t cnt, int64_t waves, int64_t t2, int64_t m_f) {
+  if (cnt <= 0 || m_f < kSplitMinEdges) return 1;
+  const int64_t most = (t2 + kWave * kTdUnroll - 1) / (kWave * kTdUnroll);
+  const int64_t k = waves / cnt;
+  return k < 1 ? 1 : (k > most ? most : k);
+}
+
 template <class RowT>
 __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, const Stage &S, int blk,
                                          int nblk, int nb_small, int nb_med,
@@ -592,13 +615,18 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     const int64_t cnt = T.cnt[kMedium];
     const int32_t *q = qc ? G.qm[1] : G.qm[0];
     const int64_t waves = (int64_t)nb_med * wpb;
-    for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < cnt; round += waves) {
-      const int64_t i = round + wib;
-      const int32_t u = i < cnt ? q[i] : -1;  // uniform within the wavefront
+    // kpv wavefronts share each row (interleaved steps) when the queue is
+    // shorter than the role's wavefronts
+    const int64_t kpv = medium_split(cnt, waves, G.t2, T.m_f);
+    const int64_t items = cnt * kpv;
+    for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < items; round += waves) {
+      const int64_t it = round + wib;
+      const int64_t i = it / kpv, sub = it - i * kpv;
+      const int32_t u = it < items ? q[i] : -1;  // uniform within the wavefront
       if (u >= 0 && (!G.slot || G.slot[u] == (int32_t)i)) {  // (culled duplicates skip)
-        if (lane == 0) fbm_clear(T.fbm, u);
+        if (lane == 0 && sub == 0) fbm_clear(T.fbm, u);
         const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
-        for (int64_t b = beg; b < end; b += (int64_t)kWave * kTdUnroll) {
+        for (int64_t b = beg + sub * kWave * kTdUnroll; b < end; b += (int64_t)kWave * kTdUnroll * kpv) {
           int32_t x[kTdUnroll], uu[kTdUnroll];
 #pragma unroll
           for (int q = 0; q < kTdUnroll; ++q) {
@@ -867,6 +895,7 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
     T.fbm = nullptr;  // top-down only: no frontier bitmap to keep
+    T.m_f = INT64_MAX;  // every workgroup takes part anyway: always split long medium rows
     T.from_bitmap = false;
     const Stage S = stage_open(lds);
     unsigned long long counts[2];
@@ -1167,15 +1196,37 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
 // kAnyDir to read it from the control block (captured loop).
 constexpr int kAnyDir = 2;
 
+// True when the level number is still `seen` (any, if negative) and is the
+// launch's (lvl_rem modulo lvl_mod), checked after every earlier load of the
+// control block has returned.
+__device__ __forceinline__ bool level_still(const Ctl *c, int32_t seen, int32_t lvl_mod, int32_t lvl_rem) {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+  const int32_t lv = __hip_atomic_load(&c->level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (seen < 0 || lv == seen) && lv % lvl_mod == lvl_rem;
+}
+
 template <class RowT, int D>
-__global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t mode) {
+__global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t mode,
+                                                   int32_t lvl_mod, int32_t lvl_rem) {
   const Ctl *c = G.ctl;
-  if (c->done || (D != kAnyDir && c->dir != D)) return;
+  if (c->done) return;
+  // This launch is for the level whose number is lvl_rem modulo lvl_mod.
+  // Workgroups of a launch can start after its level has been decided (the
+  // decide step runs as soon as the workgroups with work have finished); such
+  // a workgroup must not act on the next level's state.  So every field is
+  // read first and the level number last, once those loads have returned:
+  // the decide step writes the number before any other field, so a number
+  // that still matches means the fields were read before it ran.
+  // (Every workgroup of a bottom-up level takes part in its decide step, so
+  // none starts after it; there only the direction read needs the check.)
+  const int32_t dir = c->dir;
+  if (D != kAnyDir && dir != D) return;
   extern __shared__ __align__(16) char lds[];
   unsigned long long counts[kPartials] = {0, 0, 0, 0};
   unsigned rank = blockIdx.x, nactive = gridDim.x;
-  if (D == kTD || (D == kAnyDir && c->dir == kTD)) {
+  if (D == kTD || (D == kAnyDir && dir == kTD)) {
     const TdLevel T = td_level_state(G, c);
+    if (!level_still(c, T.level, lvl_mod, lvl_rem)) return;
     if (T.from_bitmap) {  // every workgroup takes a share of the frontier words
       const Stage S = stage_open(lds);
       int32_t *ring = reinterpret_cast<int32_t *>(lds + stage_bytes(blockDim.x)) + (threadIdx.x >> 6) * kCandTd;
@@ -1190,7 +1241,8 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
     const int64_t b = blockIdx.x;
     const int64_t nb_large = (int64_t)gridDim.x - nb_small - nb_med;
     const int64_t a_s = min((int64_t)nb_small, (T.cnt[kSmall] + blockDim.x - 1) / blockDim.x);
-    const int64_t a_m = min((int64_t)nb_med, (T.cnt[kMedium] + (blockDim.x >> 6) - 1) / (blockDim.x >> 6));
+    const int64_t m_items = T.cnt[kMedium] * medium_split(T.cnt[kMedium], (int64_t)nb_med * (blockDim.x >> 6), G.t2, T.m_f);
+    const int64_t a_m = min((int64_t)nb_med, (m_items + (blockDim.x >> 6) - 1) / (blockDim.x >> 6));
     const int64_t a_l = min(nb_large, T.cnt[kLarge]);
     int64_t r;
     if (b < nb_small) r = b < a_s ? b : -1;
@@ -1205,6 +1257,12 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
     counts[0] = tc[0];
     counts[1] = tc[1];
   } else {
+    if (D == kAnyDir) {
+      // (dir has been read and used above, so this load follows it; a
+      // bottom-up launch of the host loop has no workgroup that starts late)
+      const int32_t lv = __hip_atomic_load(&c->level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lv % lvl_mod != lvl_rem) return;
+    }
     bu_level(G, c, lds, counts);
   }
   end_level<kPartials>(G, mode, counts, rank, nactive);
@@ -1306,20 +1364,26 @@ struct TdRoles {
   int small, med, large;
 };
 
-TdRoles td_roles(const Shapes &S, int64_t c0, int64_t c1, int64_t c2) {
+TdRoles td_roles(const Shapes &S, int64_t c0, int64_t c1, int64_t c2, int64_t t2) {
   TdRoles r;
   r.small = c0 > 0 ? blocks_for(c0, S.bs, 512) : 0;
-  r.med = c1 > 0 ? blocks_for(c1, S.wpb, 256) : 0;
+  r.med = c1 > 0 ? blocks_for(c1 * medium_split(1, 1 << 30, t2, INT64_MAX), S.wpb, 256) : 0;  // room to split rows
   r.large = c2 > 0 ? blocks_for(c2, 1, 256) : 0;
   if (r.small + r.med + r.large == 0) r.small = 1;
   return r;
 }
 
 template <class RowT>
-void launch_level(const DevG<RowT> &G, const Shapes &S, int dir, int blocks, const TdRoles &r, hipStream_t st) {
+void launch_level(const DevG<RowT> &G, const Shapes &S, int dir, int blocks, const TdRoles &r, hipStream_t st,
+                  int32_t lvl_mod, int32_t lvl_rem) {
   auto *k = dir == kTD ? k_level<RowT, kTD> : dir == kBU ? k_level<RowT, kBU> : k_level<RowT, kAnyDir>;
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(S.bs), S.level_lds, st, G, r.small, r.med, (int32_t)kFusedDecide);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(S.bs), S.level_lds, st, G, r.small, r.med, (int32_t)kFusedDecide,
+                     lvl_mod, lvl_rem);
 }
+
+// Level numbers of launches that know their level exactly (host-driven and
+// queued loops); captured chunks of K levels check the level modulo K.
+constexpr int32_t kExactLevel = 1 << 30;
 
 // Waits for publication number `seq` of a device-driven run (its last
 // level).  Sets *published to false when the stream drained without it (the
@@ -1327,7 +1391,7 @@ void launch_level(const DevG<RowT> &G, const Shapes &S, int dir, int blocks, con
 int wait_final(bfs_graph *g, hipStream_t st, uint32_t seq, bool *published) {
   volatile uint32_t *p = &g->ctl_host->seq;
   for (uint64_t spin = 0;; ++spin) {
-    if (__atomic_load_n(p, __ATOMIC_ACQUIRE) == seq) {
+    if ((int32_t)(__atomic_load_n(p, __ATOMIC_ACQUIRE) - seq) >= 0) {  // (or a later one)
       *published = true;
       return BFS_OK;
     }
@@ -1336,7 +1400,7 @@ int wait_final(bfs_graph *g, hipStream_t st, uint32_t seq, bool *published) {
       if (q != hipSuccess && q != hipErrorNotReady)
         return fail(BFS_ERR_DEVICE, "level kernels failed: %s", hipGetErrorString(q));
       if (q == hipSuccess) {
-        *published = __atomic_load_n(p, __ATOMIC_ACQUIRE) == seq;
+        *published = (int32_t)(__atomic_load_n(p, __ATOMIC_ACQUIRE) - seq) >= 0;
         return BFS_OK;
       }
     }
@@ -1416,13 +1480,14 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
       BFS_HIP(hipEventRecord(e0, st));
     }
+    const int32_t level = seq == base + 1 ? 0 : h.level;
     if (h.dir == kTD && h.conv == kConvB2Q) {  // frontier read from the bitmap, word-parallel
-      launch_level(G, S, kTD, S.bu_blocks, TdRoles{0, 0, 0}, st);
+      launch_level(G, S, kTD, S.bu_blocks, TdRoles{0, 0, 0}, st, kExactLevel, level);
     } else if (h.dir == kTD) {
-      const TdRoles r = td_roles(S, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qcnt[h.qcur][2]);
-      launch_level(G, S, kTD, r.small + r.med + r.large, r, st);
+      const TdRoles r = td_roles(S, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qcnt[h.qcur][2], G.t2);
+      launch_level(G, S, kTD, r.small + r.med + r.large, r, st, kExactLevel, level);
     } else {
-      launch_level(G, S, kBU, S.bu_blocks, TdRoles{0, 0, 0}, st);
+      launch_level(G, S, kBU, S.bu_blocks, TdRoles{0, 0, 0}, st, kExactLevel, level);
     }
     if (timing) BFS_HIP(hipEventRecord(e1, st));
     BFS_HIP(hipGetLastError());
@@ -1461,7 +1526,7 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
   release_graph_exec(g);
   BFS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int l = 0; l < K; ++l) {
-    launch_level(G, S, kAnyDir, blocks, r, cs);
+    launch_level(G, S, kAnyDir, blocks, r, cs, K, l);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
@@ -1474,19 +1539,33 @@ int capture_levels(bfs_graph *g, const DevG<RowT> &G, int policy, int K) {
 
 template <class RowT>
 int graph_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy) {
-  const int K = g->params.graph_chunk_levels;
+  // (at least two levels per chunk: a launch checks its level modulo K)
+  const int K = std::max(2, (int)g->params.graph_chunk_levels);
   int rc;
   if (!g->gexec || g->gexec_levels != K) {
     if ((rc = capture_levels(g, G, policy, K))) return rc;
   }
   // the init kernel published number pub_seq + 1, the last level publishes
-  // pub_seq + 2; replay the chunk until it has
+  // pub_seq + 2; replay the chunk until it has.  Every replay of a running
+  // search advances it by K levels; now and then the host makes sure it did.
   const uint32_t target = g->pub_seq + 2;
-  for (;;) {
+  int32_t last_level = -1;
+  for (int64_t replay = 1;; ++replay) {
     BFS_HIP(hipGraphLaunch(g->gexec, st));
     bool published = false;
     if ((rc = wait_final(g, st, target, &published))) return rc;
     if (published) break;
+    if (replay % 64 == 0) {  // the stream has drained: read the level it reached
+      Ctl h;
+      BFS_HIP(hipMemcpy(&h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+      if (h.level == last_level || h.done)
+        return fail(BFS_ERR_DEVICE,
+                    "the captured level loop stopped advancing at level %d (done %d, direction %d, "
+                    "queue counts %u/%u/%u, %lld replays)",
+                    h.level, h.done, h.dir, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qcnt[h.qcur][2],
+                    (long long)replay);
+      last_level = h.level;
+    }
   }
   return BFS_OK;
 }
@@ -1517,10 +1596,10 @@ int queued_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, int policy, s
       hipEvent_t e0 = level_event(g, 2 * (size_t)enq), e1 = level_event(g, 2 * (size_t)enq + 1);
       if (!e0 || !e1) return fail(BFS_ERR_DEVICE, "hipEventCreate failed");
       BFS_HIP(hipEventRecord(e0, st));
-      launch_level(G, S, kAnyDir, blocks, r, st);
+      launch_level(G, S, kAnyDir, blocks, r, st, kExactLevel, enq);
       BFS_HIP(hipEventRecord(e1, st));
     } else {
-      launch_level(G, S, kAnyDir, blocks, r, st);
+      launch_level(G, S, kAnyDir, blocks, r, st, kExactLevel, enq);
     }
     BFS_HIP(hipGetLastError());
     ++enq;

@@ -340,10 +340,11 @@ def test_td_visited_dist_cas(rmat16, loop):
     the oracle's top-down-only replay."""
     bfs = library()
     say("td_visited dist_cas, loop", loop)
-    for g in (rmat16, graphgen.grid(256), graphs.path(500)[0]):
+    for name, g in (("rmat16", rmat16), ("grid256", graphgen.grid(256)), ("path500", graphs.path(500)[0])):
         gh = upload(g)
         bfs.bfs_set_params(gh, policy=3, loop=loop, td_visited=bfs.BFS_TD_DIST_CAS)
         for s in graphgen.sources(g, 3, seed=7):
+            say("  graph", name, "source", int(s))
             check_single(g, gh, s)
         gh.close()
 
