@@ -152,8 +152,10 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   const int64_t bytes = (int64_t)A.k * A.n;
   const int64_t head = A.aligned4 ? bytes / 4 : 0;  // 4-byte stores when the rows allow it
   uint32_t *d32 = reinterpret_cast<uint32_t *>(A.dist8);
-  for (int64_t i = tid; i < head; i += nthreads) d32[i] = 0xFFFFFFFFu;
-  for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) A.dist8[i] = 255;
+  // (streaming stores: the rows are written once more, byte by byte, and
+  // never read here)
+  for (int64_t i = tid; i < head; i += nthreads) __builtin_nontemporal_store(0xFFFFFFFFu, d32 + i);
+  for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) __builtin_nontemporal_store((uint8_t)255, A.dist8 + i);
   if (tid == 0) {
     c->dir = 0;
     c->done = 0;
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
       while (any) {  // one coalesced byte row segment per search that advanced
         const int i = __ffsll((unsigned long long)any) - 1;
         any &= any - 1;
-        if ((nb >> i) & 1ull) A.dist8[(int64_t)i * A.n + v] = dval;
+        if ((nb >> i) & 1ull) __builtin_nontemporal_store(dval, A.dist8 + (int64_t)i * A.n + v);
       }
     }
     pairs = wave_sum(pairs);

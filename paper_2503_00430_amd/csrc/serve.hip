@@ -151,8 +151,9 @@ __global__ void k_sv_join(SvArgs<RowT> A) {
     while (b) {
       const int i = __ffsll((unsigned long long)b) - 1;
       b &= b - 1;
-      c->dist[i][v] = -1;
-      if (c->parent[i]) c->parent[i][v] = -1;
+      // (streaming stores: output rows, never read by the server)
+      __builtin_nontemporal_store(-1, c->dist[i] + v);
+      if (c->parent[i]) __builtin_nontemporal_store(-1, c->parent[i] + v);
     }
   }
 }
@@ -188,7 +189,7 @@ __device__ __forceinline__ void write_parents(const ServeCtl *c, uint64_t bits, 
   while (bits) {
     const int i = __ffsll((unsigned long long)bits) - 1;
     bits &= bits - 1;
-    c->parent[i][x] = u;
+    __builtin_nontemporal_store(u, c->parent[i] + x);
   }
 }
 
@@ -310,7 +311,7 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
               const uint64_t who = __ballot((fr >> i) & 1ull);
               const int src = __ffsll((unsigned long long)who) - 1;
               const int32_t px = __shfl(x, src);
-              if (lane == 0) c->parent[i][vl] = px;
+              if (lane == 0) __builtin_nontemporal_store(px, c->parent[i] + vl);
             }
           }
           al |= fresh;
@@ -372,7 +373,7 @@ __global__ void k_sv_finalize(SvArgs<RowT> A) {
         while (b) {
           const int k = __ffsll((unsigned long long)b) - 1;
           b &= b - 1;
-          c->dist[k][x] = level + 1 - c->start[k];
+          __builtin_nontemporal_store(level + 1 - c->start[k], c->dist[k] + x);
         }
       }
     }
