@@ -44,6 +44,11 @@ namespace {
 
 constexpr int kLanes = 64;
 constexpr int kSvMaxBlocks = 1024;
+// Top-down rows longer than kSvChunk edges are expanded as kSvChunk-edge
+// chunks spread over every wavefront of the grid (a hub's row walked by one
+// wavefront would take one dependent step per 64 edges: tens of
+// milliseconds for a million-edge hub).
+constexpr int64_t kSvChunk = 512;
 
 struct alignas(256) ServeCtl {
   int32_t dir;    // direction of the next level (0 top-down, 1 bottom-up)
@@ -63,6 +68,7 @@ struct alignas(256) ServeCtl {
   int32_t *parent[kLanes];
   int32_t levels_run;
   int32_t bu_percent;
+  unsigned int hcnt[2];  // entries in chunk queue 0 / 1 (rows longer than kSvChunk)
 };
 
 template <class RowT>
@@ -72,6 +78,8 @@ struct SvArgs {
   int64_t n, nnz;
   uint64_t *seen, *front, *next;
   int32_t *fq[2];  // frontier queues
+  uint64_t *hq[2];  // chunk queues of the long rows of each frontier: chunk << 32 | v
+  int64_t hq_cap;
   int32_t *tq;     // touched list
   unsigned long long *partials;  // [kSvMaxBlocks][3]
   ServeCtl *ctl;
@@ -124,6 +132,19 @@ __device__ __forceinline__ void stage1_push(const Stage1 &S, bool p, int32_t v, 
   }
 }
 
+// Appends the kSvChunk-edge chunks of frontier vertex v (degree deg) to
+// chunk queue `sel`.  The queue holds every chunk of one level: each of its
+// vertices has degree > kSvChunk, so a level has fewer than 2 nnz / kSvChunk
+// chunks; entries past hq_cap are never written.
+template <class RowT>
+__device__ __forceinline__ void push_chunks(const SvArgs<RowT> &A, ServeCtl *c, int sel, int32_t v, int64_t deg) {
+  const unsigned nch = (unsigned)((deg + kSvChunk - 1) / kSvChunk);
+  const unsigned base = atomicAdd(&c->hcnt[sel], nch);
+  uint64_t *hq = sel ? A.hq[1] : A.hq[0];
+  for (unsigned k = 0; k < nch; ++k)
+    if ((int64_t)(base + k) < A.hq_cap) hq[base + k] = ((uint64_t)k << 32) | (uint32_t)v;
+}
+
 // All threads of the workgroup call.
 __device__ __forceinline__ void stage1_flush(const Stage1 &S, int32_t *gq, unsigned *gcnt) {
   __shared__ unsigned gbase, count;
@@ -172,6 +193,8 @@ __global__ void k_sv_seed(SvArgs<RowT> A) {
     if (old == 0) {  // s is not on the frontier yet: append it once
       const unsigned slot = atomicAdd(&c->fcnt[c->fsel], 1u);
       A.fq[c->fsel][slot] = s;
+      const int64_t deg = (int64_t)A.rp[s + 1] - (int64_t)A.rp[s];
+      if (deg > kSvChunk) push_chunks(A, c, c->fsel, s, deg);
     }
     c->dist[i][s] = 0;
     if (c->parent[i]) c->parent[i][s] = s;
@@ -212,14 +235,19 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
     const int64_t nf = c->fcnt[c->fsel];
     for (int64_t base = gw * kWave; base < nf; base += nwaves * kWave) {
       const int64_t i = base + lane;
-      const int32_t v = i < nf ? fq[i] : -1;
+      int32_t v = i < nf ? fq[i] : -1;
       uint64_t f = 0;
       int64_t beg = 0, end = 0;
       if (v >= 0) {
-        f = A.front[v];
-        A.front[v] = 0;  // only this lane reads v's set during a top-down level
         beg = (int64_t)A.rp[v];
         end = (int64_t)A.rp[v + 1];
+        if (end - beg > kSvChunk) {  // a long row: its chunks are expanded below
+          v = -1;
+          beg = end = 0;
+        } else {
+          f = A.front[v];
+          A.front[v] = 0;  // only this lane reads v's set during a top-down level
+        }
       }
       const bool heavy = (end - beg) > kWave;
       bool any_push = false;
@@ -265,6 +293,32 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
         }
       }
       (void)any_push;
+    }
+    // the long rows, one kSvChunk-edge chunk per wavefront (their sets are
+    // cleared after the level, by k_sv_clear)
+    const uint64_t *hq = c->fsel ? A.hq[1] : A.hq[0];
+    const int64_t nh = min((int64_t)c->hcnt[c->fsel], A.hq_cap);
+    for (int64_t i = gw; i < nh; i += nwaves) {
+      const uint64_t e = hq[i];
+      const int32_t vl = (int32_t)(uint32_t)e;
+      const uint64_t fl = A.front[vl];
+      const int64_t b0 = (int64_t)A.rp[vl] + (int64_t)(e >> 32) * kSvChunk;
+      const int64_t e0 = min((int64_t)A.rp[vl + 1], b0 + kSvChunk);
+      for (int64_t b = b0; b < e0; b += kWave) {
+        const int64_t j = b + lane;
+        int32_t x = 0;
+        bool first = false;
+        if (j < e0) {
+          x = A.col[j];
+          const uint64_t nb = fl & ~A.seen[x];
+          if (nb) {
+            const uint64_t old = atomicOr(reinterpret_cast<unsigned long long *>(A.next + x), nb);
+            first = (old == 0);
+            if (nb & pmask & ~old) write_parents(c, nb & pmask & ~old, x, vl);
+          }
+        }
+        stage1_push(S, first, x, A.tq, &cw->tcnt);
+      }
     }
   } else {
     // Bottom-up over all vertices, one 64-vertex group per wavefront step.
@@ -331,11 +385,19 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
 template <class RowT>
 __global__ void k_sv_clear(SvArgs<RowT> A) {
   const ServeCtl *c = A.ctl;
-  if (!c->alive || c->dir != 1) return;
+  if (!c->alive) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c->dir != 1) {  // top-down: the long rows' sets (the others were cleared as read)
+    const uint64_t *hq = c->fsel ? A.hq[1] : A.hq[0];
+    const int64_t nh = min((int64_t)c->hcnt[c->fsel], A.hq_cap);
+    for (int64_t i = tid; i < nh; i += stride)
+      if ((hq[i] >> 32) == 0) A.front[(int32_t)(uint32_t)hq[i]] = 0;
+    return;
+  }
   const int32_t *fq = c->fsel ? A.fq[1] : A.fq[0];
   const int64_t nf = c->fcnt[c->fsel];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) A.front[fq[i]] = 0;
+  for (int64_t i = tid; i < nf; i += stride) A.front[fq[i]] = 0;
 }
 
 // Touched vertices become the new frontier.
@@ -367,7 +429,9 @@ __global__ void k_sv_finalize(SvArgs<RowT> A) {
       if (nb) {
         A.seen[x] = s | nb;
         pairs += (unsigned long long)__popcll(nb);
-        fedges += (unsigned long long)((int64_t)A.rp[x + 1] - (int64_t)A.rp[x]);
+        const int64_t deg = (int64_t)A.rp[x + 1] - (int64_t)A.rp[x];
+        fedges += (unsigned long long)deg;
+        if (deg > kSvChunk) push_chunks(A, cw, nsel, x, deg);
         bits |= nb;
         uint64_t b = nb;
         while (b) {
@@ -441,6 +505,7 @@ __global__ void __launch_bounds__(1024) k_sv_decide(SvArgs<RowT> A, int32_t nblo
   }
   c->alive = tb;
   c->fcnt[c->fsel] = 0;
+  c->hcnt[c->fsel] = 0;
   c->fsel ^= 1;
   c->tcnt = 0;
   c->level += 1;
@@ -477,6 +542,8 @@ struct Batch {
   hipEvent_t ev = nullptr;
   uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
   int32_t *fq[2] = {nullptr, nullptr};
+  uint64_t *hq[2] = {nullptr, nullptr};
+  int64_t hq_cap = 0;
   int32_t *tq = nullptr;
   unsigned long long *partials = nullptr;
   ServeCtl *ctl = nullptr;       // device
@@ -487,8 +554,13 @@ struct Batch {
   size_t bytes = 0;
 };
 
+// Chunk entries one level can hold: every chunked row has more than
+// kSvChunk edges, so its chunks number under 2 deg / kSvChunk.
+int64_t chunk_capacity(const bfs_graph *g) { return 2 * (g->nnz / kSvChunk) + 2 * kLanes; }
+
 size_t batch_bytes(const bfs_graph *g) {
-  return (size_t)g->n * (3 * 8 + 3 * 4) + sizeof(unsigned long long) * kSvMaxBlocks * 3 + sizeof(ServeCtl);
+  return (size_t)g->n * (3 * 8 + 3 * 4) + 2 * sizeof(uint64_t) * (size_t)chunk_capacity(g) +
+         sizeof(unsigned long long) * kSvMaxBlocks * 3 + sizeof(ServeCtl);
 }
 
 }  // namespace
@@ -516,7 +588,7 @@ namespace {
 void free_batch(Batch *b) {
   DeviceGuard dg(b->g->device);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  void *ptrs[] = {b->seen, b->front, b->next, b->fq[0], b->fq[1], b->tq, b->partials, b->ctl};
+  void *ptrs[] = {b->seen, b->front, b->next, b->fq[0], b->fq[1], b->hq[0], b->hq[1], b->tq, b->partials, b->ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->mirror) (void)hipHostFree(b->mirror);
@@ -531,11 +603,14 @@ bool make_batch(Batch *b, bfs_graph *g) {
   const size_t n = (size_t)g->n;
   bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
+  b->hq_cap = chunk_capacity(g);
   void **dst[] = {(void **)&b->seen, (void **)&b->front, (void **)&b->next, (void **)&b->fq[0],
-                  (void **)&b->fq[1], (void **)&b->tq, (void **)&b->partials, (void **)&b->ctl};
+                  (void **)&b->fq[1], (void **)&b->tq, (void **)&b->partials, (void **)&b->ctl,
+                  (void **)&b->hq[0], (void **)&b->hq[1]};
   const size_t sizes[] = {8 * n, 8 * n, 8 * n, 4 * n, 4 * n, 4 * n,
-                          sizeof(unsigned long long) * kSvMaxBlocks * 3, sizeof(ServeCtl)};
-  for (int i = 0; i < 8 && ok; ++i) ok = hipMalloc(dst[i], std::max<size_t>(sizes[i], 8)) == hipSuccess;
+                          sizeof(unsigned long long) * kSvMaxBlocks * 3, sizeof(ServeCtl),
+                          sizeof(uint64_t) * (size_t)b->hq_cap, sizeof(uint64_t) * (size_t)b->hq_cap};
+  for (int i = 0; i < 10 && ok; ++i) ok = hipMalloc(dst[i], std::max<size_t>(sizes[i], 8)) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&b->mirror, sizeof(ServeCtl), hipHostMallocDefault) == hipSuccess;
   if (ok) {
     ok = hipMemsetAsync(b->seen, 0, 8 * n, b->stream) == hipSuccess &&
@@ -561,6 +636,9 @@ SvArgs<RowT> args_of(Batch *b) {
   A.next = b->next;
   A.fq[0] = b->fq[0];
   A.fq[1] = b->fq[1];
+  A.hq[0] = b->hq[0];
+  A.hq[1] = b->hq[1];
+  A.hq_cap = b->hq_cap;
   A.tq = b->tq;
   A.partials = b->partials;
   A.ctl = b->ctl;

@@ -574,16 +574,18 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
 // Ends with the staged queue entries flushed and the workgroup's counts in
 // `counts`.  All threads of the workgroup call it.
 // Wavefronts per medium vertex: as many as the role has per queued vertex,
-// at most one per kWave * kTdUnroll edges of the longest medium row (t2).
-// A level whose whole frontier has fewer than kSplitMinEdges edges keeps one
-// wavefront per vertex: there the split would only wake more workgroups
-// (and take the level off the single-workgroup decide).
-constexpr int64_t kSplitMinEdges = 1024;
+// at most one per kWave * kTdUnroll edges of the longest row it can hold:
+// a medium row (t2 edges at most) and no longer than the whole frontier's
+// degree sum m_f (so a small level keeps a single workgroup and its
+// single-workgroup decide).
 __host__ __device__ inline int64_t medium_split(int64_t cnt, int64_t waves, int64_t t2, int64_t m_f) {
-  if (cnt <= 0 || m_f < kSplitMinEdges) return 1;
-  const int64_t most = (t2 + kWave * kTdUnroll - 1) / (kWave * kTdUnroll);
+  if (cnt <= 0) return 1;
+  constexpr int64_t step = kWave * kTdUnroll;
+  const int64_t rows = m_f < t2 ? m_f : t2;
+  const int64_t most = (rows + step - 1) / step;
   const int64_t k = waves / cnt;
-  return k < 1 ? 1 : (k > most ? most : k);
+  const int64_t kpv = k < most ? k : most;
+  return kpv < 1 ? 1 : kpv;
 }
 
 template <class RowT>

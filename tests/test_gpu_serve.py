@@ -48,6 +48,9 @@ def pool(bfs):
         "path700": graphs.path(700)[0],
         "urand4k": graphgen.urand(1 << 12, 8),
         "two_paths": graphs.two_paths(40, 30)[0],
+        # a 1000-edge row next to the source: top-down levels expand it in
+        # chunks spread over the grid
+        "long_row": graphs.deferred_rows(n=4096, nf=1500, seed=5)[0],
     }
     handles = {k: upload(g) for k, g in gs.items()}
     yield gs, handles
@@ -117,6 +120,23 @@ def test_alone_equals_mix(bfs, pool):
     assert max(st["batch_lanes"] for st in stats.values()) > 1  # requests did share batches
     bfs.bfs_serve_destroy(srv)
     torch.cuda.synchronize()
+
+
+def test_long_rows_in_chunks(bfs, pool):
+    """Sources on and next to rows longer than the server's chunk length,
+    alone and sharing a batch."""
+    gs, handles = pool
+    g = gs["long_row"]
+    big = np.flatnonzero(g.degree > 512)
+    assert len(big) > 0
+    srv = bfs.bfs_serve_create(1 << 34, 64)
+    say("serve: long rows in chunks")
+    srcs = [0] + [int(x) for x in big[:3]] + [int(g.col_idx[g.row_ptr[int(big[0])]])]
+    outs = [submit(bfs, srv, gs, handles, "long_row", s, True) for s in srcs]
+    wait_all(bfs, srv, [t for t, _, _ in outs])
+    for s, (t, d, p) in zip(srcs, outs):
+        check(gs, "long_row", s, d, p)
+    bfs.bfs_serve_destroy(srv)
 
 
 def test_lanes_join_long_search(bfs, pool):
