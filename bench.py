@@ -107,6 +107,31 @@ def cpu_baseline(g, sources, budget_s=20.0, max_sources=8):
                       f"serial FIFO BFS with parents, {t_total:.1f} s of CPU time"}
 
 
+def cpu_openmp(g, sources, budget_s=8.0, max_sources=4):
+    """The paper's three CPU kernels in OpenMP (cpu_context/bfs_omp.c) on the
+    host's cores, with parents: harmonic-mean GTEPS over a bounded sample of
+    the workload's sources (a context figure beside the serial-oracle
+    baseline, not a baseline of the GPU kernels)."""
+    import cpu_context
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    edges = {}
+    out = {"threads": threads, "unit": "GTEPS"}
+    for kind in ("conventional", "hybrid", "visited_bitmap"):
+        teps, t_total = [], 0.0
+        for s in sources[:max_sources]:
+            d, _, secs, _ = cpu_context.bfs(g, int(s), kind, threads)
+            if int(s) not in edges:
+                edges[int(s)] = oracle.level_stats(g, d)["m_s"]
+            teps.append(edges[int(s)] / secs)
+            t_total += secs
+            if t_total > budget_s:
+                break
+        out[kind] = {"gteps_hm": round(len(teps) / sum(1.0 / t for t in teps) / 1e9, 4),
+                     "sources": len(teps), "seconds": round(t_total, 2)}
+    return out
+
+
 def bench_batched(bfs, torch, reps=3):
     """RMAT scale 22, 64 sources: one bfs_run_batch against 64 bfs_run calls."""
     g, sources, _ = make_graph("rmat22")
@@ -521,6 +546,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, sources)
+        log("cpu context (OpenMP kernels of the paper)")
+        out["cpu_openmp_context"] = cpu_openmp(g, sources)
     print(json.dumps(out), flush=True)
 
 
