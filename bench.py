@@ -203,14 +203,17 @@ TD_VISITED = {0: "VisitedBitmap (bitmap, atomic OR)", 1: "Conventional (CAS on d
 def ablation(bfs, torch, gh, sources, reps=1):
     """Section 2's visited tests as top-down-only searches on the same
     sources (captured loop): harmonic-mean GTEPS, and for the non-atomic
-    test the share of duplicate frontier entries it created (frontier
-    entries over the bitmap run's, minus one)."""
+    tests the share of duplicate frontier entries they created (frontier
+    entries over the bitmap run's, minus one), overall and per level for the
+    first source as in the paper's Figure 1 (duplicates in % of the distinct
+    frontier; for long searches a summary, with the levels whose frontier
+    is under 1 % of N apart)."""
     params = bfs.bfs_get_params(gh)
     dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
-    out, nf_base = {}, None
+    out, nf_base, per_level_base = {}, None, None
     for mode, name in TD_VISITED.items():
         bfs.bfs_set_params(gh, policy=bfs.BFS_POLICY_TD_ONLY, td_visited=mode)
-        per, nf = {}, 0
+        per, nf, first_levels = {}, 0, None
         try:
             bfs.bfs_run(gh, int(sources[0]), dist)
             for _ in range(reps):
@@ -219,6 +222,8 @@ def ablation(bfs, torch, gh, sources, reps=1):
                     run, lvs = bfs.bfs_get_run_stats(gh)
                     per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
                     nf += sum(lv["frontier"] for lv in lvs)
+                    if first_levels is None:
+                        first_levels = np.array([lv["frontier"] for lv in lvs], dtype=np.float64)
         except bfs.BfsError as e:  # e.g. duplicates outgrowing the queues
             out[name] = {"error": str(e)}
             continue
@@ -226,9 +231,20 @@ def ablation(bfs, torch, gh, sources, reps=1):
         if nf_base is None:
             edges = {s: e for s, (e, _) in per.items()}
             nf_base = nf
+            per_level_base = first_levels
         teps = [edges[s] / statistics.median(t) for s, (_, t) in per.items()]
         out[name] = {"gteps_hm": round(len(teps) / sum(1.0 / t for t in teps) / 1e9, 3),
                      "duplicate_frontier_share": round(nf / nf_base - 1.0, 5)}
+        if mode >= 2 and len(first_levels) == len(per_level_base):
+            pct = 100.0 * (first_levels / per_level_base - 1.0)
+            small = per_level_base < 0.01 * gh.n
+            if len(pct) <= 16:
+                out[name]["duplicates_pct_per_level_first_source"] = [round(float(x), 2) for x in pct]
+            else:
+                out[name]["duplicates_pct_first_source"] = {
+                    "levels": int(len(pct)), "mean": round(float(pct.mean()), 2), "max": round(float(pct.max()), 2),
+                    "mean_where_frontier_under_1pct_of_n": round(float(pct[small].mean()), 2) if small.any() else None,
+                    "mean_elsewhere": round(float(pct[~small].mean()), 2) if (~small).any() else None}
     bfs.bfs_set_params(gh, **params)
     return out
 
