@@ -18,8 +18,11 @@
 //             to unseen neighbours (atomicOr into next[x]; the first pusher
 //             of x appends it to the touched list); bottom-up: every vertex
 //             with unfinished live lanes gathers its neighbours' frontier
-//             sets, stopping once all its missing lanes are found;
-//   clear     bottom-up only: the old frontier's sets are cleared;
+//             sets, stopping once all its missing lanes are found.  The
+//             frontier sets alternate between two arrays by level parity;
+//             expand also clears, in the other array, the sets of the
+//             previous level's frontier (that array receives the next
+//             frontier);
 //   finalize  touched vertices: new lanes become seen and frontier, their
 //             distances are written, the vertex joins the next frontier
 //             queue;
@@ -69,6 +72,7 @@ struct alignas(256) ServeCtl {
   int32_t levels_run;
   int32_t bu_percent;
   unsigned int hcnt[2];  // entries in chunk queue 0 / 1 (rows longer than kSvChunk)
+  unsigned int pcnt;     // entries of the previous level's frontier (queue fsel ^ 1)
 };
 
 template <class RowT>
@@ -76,7 +80,8 @@ struct SvArgs {
   const RowT *rp;
   const int32_t *col;
   int64_t n, nnz;
-  uint64_t *seen, *front, *next;
+  uint64_t *seen, *next;
+  uint64_t *fr[2];  // frontier sets of even / odd batch levels
   int32_t *fq[2];  // frontier queues
   uint64_t *hq[2];  // chunk queues of the long rows of each frontier: chunk << 32 | v
   int64_t hq_cap;
@@ -189,7 +194,7 @@ __global__ void k_sv_seed(SvArgs<RowT> A) {
     const int32_t s = c->join_src[i];
     const unsigned long long bit = 1ull << i;
     atomicOr(reinterpret_cast<unsigned long long *>(A.seen + s), bit);
-    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
+    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(A.fr[c->level & 1] + s), bit);
     if (old == 0) {  // s is not on the frontier yet: append it once
       const unsigned slot = atomicAdd(&c->fcnt[c->fsel], 1u);
       A.fq[c->fsel][slot] = s;
@@ -229,6 +234,14 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
   const int64_t wpb = blockDim.x >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * wpb;
   const int64_t gw = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint64_t *front = A.fr[c->level & 1];
+  {  // the previous frontier's sets, in the array the next frontier goes to
+    uint64_t *stale = A.fr[(c->level & 1) ^ 1];
+    const int32_t *pq = c->fsel ? A.fq[0] : A.fq[1];
+    const int64_t np = c->pcnt;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) stale[pq[i]] = 0;
+  }
   if (c->dir == 0) {
     // Top-down over the frontier queue, 64 entries per wavefront step.
     const int32_t *fq = c->fsel ? A.fq[1] : A.fq[0];
@@ -245,8 +258,7 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
           v = -1;
           beg = end = 0;
         } else {
-          f = A.front[v];
-          A.front[v] = 0;  // only this lane reads v's set during a top-down level
+          f = front[v];
         }
       }
       const bool heavy = (end - beg) > kWave;
@@ -294,14 +306,13 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
       }
       (void)any_push;
     }
-    // the long rows, one kSvChunk-edge chunk per wavefront (their sets are
-    // cleared after the level, by k_sv_clear)
+    // the long rows, one kSvChunk-edge chunk per wavefront
     const uint64_t *hq = c->fsel ? A.hq[1] : A.hq[0];
     const int64_t nh = min((int64_t)c->hcnt[c->fsel], A.hq_cap);
     for (int64_t i = gw; i < nh; i += nwaves) {
       const uint64_t e = hq[i];
       const int32_t vl = (int32_t)(uint32_t)e;
-      const uint64_t fl = A.front[vl];
+      const uint64_t fl = front[vl];
       const int64_t b0 = (int64_t)A.rp[vl] + (int64_t)(e >> 32) * kSvChunk;
       const int64_t e0 = min((int64_t)A.rp[vl + 1], b0 + kSvChunk);
       for (int64_t b = b0; b < e0; b += kWave) {
@@ -336,7 +347,7 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
       if (target && !heavy) {
         for (int64_t j = beg; j < end; ++j) {
           const int32_t x = A.col[j];
-          const uint64_t fr = A.front[x] & target & ~acc;
+          const uint64_t fr = front[x] & target & ~acc;
           if (fr) {
             if (fr & pmask) write_parents(c, fr & pmask, v, x);
             acc |= fr;
@@ -355,7 +366,7 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
         for (int64_t b = b0; b < e0; b += kWave) {
           const int64_t j = b + lane;
           const int32_t x = j < e0 ? A.col[j] : 0;
-          const uint64_t fr = j < e0 ? (A.front[x] & tl) : 0ull;
+          const uint64_t fr = j < e0 ? (front[x] & tl) : 0ull;
           uint64_t fresh = wave_or(fr) & ~al;
           if (fresh & pmask) {  // parent of each new lane: its lowest contributing position
             uint64_t pb = fresh & pmask;
@@ -379,25 +390,6 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
     }
   }
   stage1_flush(S, A.tq, &cw->tcnt);
-}
-
-// Bottom-up levels: clear the frontier sets of the old frontier.
-template <class RowT>
-__global__ void k_sv_clear(SvArgs<RowT> A) {
-  const ServeCtl *c = A.ctl;
-  if (!c->alive) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c->dir != 1) {  // top-down: the long rows' sets (the others were cleared as read)
-    const uint64_t *hq = c->fsel ? A.hq[1] : A.hq[0];
-    const int64_t nh = min((int64_t)c->hcnt[c->fsel], A.hq_cap);
-    for (int64_t i = tid; i < nh; i += stride)
-      if ((hq[i] >> 32) == 0) A.front[(int32_t)(uint32_t)hq[i]] = 0;
-    return;
-  }
-  const int32_t *fq = c->fsel ? A.fq[1] : A.fq[0];
-  const int64_t nf = c->fcnt[c->fsel];
-  for (int64_t i = tid; i < nf; i += stride) A.front[fq[i]] = 0;
 }
 
 // Touched vertices become the new frontier.
@@ -425,7 +417,7 @@ __global__ void k_sv_finalize(SvArgs<RowT> A) {
       const uint64_t s = A.seen[x];
       nb = A.next[x] & ~s;
       A.next[x] = 0;
-      A.front[x] = nb;
+      A.fr[(level & 1) ^ 1][x] = nb;
       if (nb) {
         A.seen[x] = s | nb;
         pairs += (unsigned long long)__popcll(nb);
@@ -504,6 +496,7 @@ __global__ void __launch_bounds__(1024) k_sv_decide(SvArgs<RowT> A, int32_t nblo
     c->finish[i] = c->level + 1;
   }
   c->alive = tb;
+  c->pcnt = c->fcnt[c->fsel];
   c->fcnt[c->fsel] = 0;
   c->hcnt[c->fsel] = 0;
   c->fsel ^= 1;
@@ -540,7 +533,7 @@ struct Batch {
   bfs_graph *g = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
-  uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+  uint64_t *seen = nullptr, *fr[2] = {nullptr, nullptr}, *next = nullptr;
   int32_t *fq[2] = {nullptr, nullptr};
   uint64_t *hq[2] = {nullptr, nullptr};
   int64_t hq_cap = 0;
@@ -559,7 +552,7 @@ struct Batch {
 int64_t chunk_capacity(const bfs_graph *g) { return 2 * (g->nnz / kSvChunk) + 2 * kLanes; }
 
 size_t batch_bytes(const bfs_graph *g) {
-  return (size_t)g->n * (3 * 8 + 3 * 4) + 2 * sizeof(uint64_t) * (size_t)chunk_capacity(g) +
+  return (size_t)g->n * (4 * 8 + 3 * 4) + 2 * sizeof(uint64_t) * (size_t)chunk_capacity(g) +
          sizeof(unsigned long long) * kSvMaxBlocks * 3 + sizeof(ServeCtl);
 }
 
@@ -588,7 +581,8 @@ namespace {
 void free_batch(Batch *b) {
   DeviceGuard dg(b->g->device);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  void *ptrs[] = {b->seen, b->front, b->next, b->fq[0], b->fq[1], b->hq[0], b->hq[1], b->tq, b->partials, b->ctl};
+  void *ptrs[] = {b->seen, b->fr[0], b->fr[1], b->next, b->fq[0], b->fq[1], b->hq[0], b->hq[1], b->tq,
+                  b->partials, b->ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->mirror) (void)hipHostFree(b->mirror);
@@ -604,17 +598,18 @@ bool make_batch(Batch *b, bfs_graph *g) {
   bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
   b->hq_cap = chunk_capacity(g);
-  void **dst[] = {(void **)&b->seen, (void **)&b->front, (void **)&b->next, (void **)&b->fq[0],
+  void **dst[] = {(void **)&b->seen, (void **)&b->fr[0], (void **)&b->next, (void **)&b->fq[0],
                   (void **)&b->fq[1], (void **)&b->tq, (void **)&b->partials, (void **)&b->ctl,
-                  (void **)&b->hq[0], (void **)&b->hq[1]};
+                  (void **)&b->hq[0], (void **)&b->hq[1], (void **)&b->fr[1]};
   const size_t sizes[] = {8 * n, 8 * n, 8 * n, 4 * n, 4 * n, 4 * n,
                           sizeof(unsigned long long) * kSvMaxBlocks * 3, sizeof(ServeCtl),
-                          sizeof(uint64_t) * (size_t)b->hq_cap, sizeof(uint64_t) * (size_t)b->hq_cap};
-  for (int i = 0; i < 10 && ok; ++i) ok = hipMalloc(dst[i], std::max<size_t>(sizes[i], 8)) == hipSuccess;
+                          sizeof(uint64_t) * (size_t)b->hq_cap, sizeof(uint64_t) * (size_t)b->hq_cap, 8 * n};
+  for (int i = 0; i < 11 && ok; ++i) ok = hipMalloc(dst[i], std::max<size_t>(sizes[i], 8)) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&b->mirror, sizeof(ServeCtl), hipHostMallocDefault) == hipSuccess;
   if (ok) {
     ok = hipMemsetAsync(b->seen, 0, 8 * n, b->stream) == hipSuccess &&
-         hipMemsetAsync(b->front, 0, 8 * n, b->stream) == hipSuccess &&
+         hipMemsetAsync(b->fr[0], 0, 8 * n, b->stream) == hipSuccess &&
+         hipMemsetAsync(b->fr[1], 0, 8 * n, b->stream) == hipSuccess &&
          hipMemsetAsync(b->next, 0, 8 * n, b->stream) == hipSuccess &&
          hipMemsetAsync(b->partials, 0, sizes[6], b->stream) == hipSuccess;
     std::memset(b->mirror, 0, sizeof(ServeCtl));
@@ -632,7 +627,8 @@ SvArgs<RowT> args_of(Batch *b) {
   A.n = b->g->n;
   A.nnz = b->g->nnz;
   A.seen = b->seen;
-  A.front = b->front;
+  A.fr[0] = b->fr[0];
+  A.fr[1] = b->fr[1];
   A.next = b->next;
   A.fq[0] = b->fq[0];
   A.fq[1] = b->fq[1];
@@ -661,7 +657,6 @@ int issue_chunk(Batch *b, int levels) {
   }
   for (int l = 0; l < levels; ++l) {
     hipLaunchKernelGGL(k_sv_expand<RowT>, dim3(nblocks), dim3(bs), lds, st, A);
-    hipLaunchKernelGGL(k_sv_clear<RowT>, dim3(nblocks), dim3(bs), 0, st, A);
     hipLaunchKernelGGL(k_sv_finalize<RowT>, dim3(nblocks), dim3(bs), lds, st, A);
     hipLaunchKernelGGL(k_sv_decide<RowT>, dim3(1), dim3(1024), 0, st, A, nblocks);
   }
