@@ -434,15 +434,29 @@ __device__ __forceinline__ void fbm_clear(uint64_t *fbm, int32_t u) {
   if (fbm) atomicAnd(reinterpret_cast<unsigned long long *>(fbm + (u >> 6)), ~(1ull << (u & 63)));
 }
 
+// Levels whose frontier has fewer edges than this claim with the atomic
+// alone: reading the visited word first saves the atomics on vertices
+// already visited, which only pays where there are many; on small levels
+// it is one more dependent round trip (the lattice's levels: -5 %).
+constexpr int64_t kPreloadMinEdges = 65536;
+
 template <class RowT>
 __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
                                          int32_t *dist, int32_t *parent, uint64_t *fbm, bool has, int32_t u,
-                                         int32_t v, unsigned long long &nfound, unsigned long long &dfound) {
+                                         int32_t v, bool preload, unsigned long long &nfound,
+                                         unsigned long long &dfound) {
   bool win = false;
   int64_t deg = 0;
   bool claimed = false;
   if (has) {
-    if (G.td_visited == BFS_TD_VISITED_BITMAP) claimed = claim(G.vis, v);
+    if (G.td_visited == BFS_TD_VISITED_BITMAP) {
+      if (preload) {
+        claimed = claim(G.vis, v);
+      } else {
+        const uint64_t bit = 1ull << (v & 63);
+        claimed = !(atomicOr(reinterpret_cast<unsigned long long *>(G.vis + (v >> 6)), (unsigned long long)bit) & bit);
+      }
+    }
     else if (G.td_visited == BFS_TD_DIST_CAS) claimed = atomicCAS(dist + v, -1, level + 1) == -1;
     else claimed = dist[v] < 0;  // plain test: racing discoverers may all pass
   }
@@ -467,6 +481,7 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
 //                                 reading the row 64 neighbours at a time;
 //   the rest                      workgroup per t2-edge chunk of a larger
 //                                 vertex.
+
 // Level state a top-down level needs, read once per level.
 struct TdLevel {
   int32_t qcur, level;
@@ -513,7 +528,7 @@ __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage 
     uint32_t *vis32 = reinterpret_cast<uint32_t *>(G.vis);
     uint32_t w[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) w[k] = x[k] >= 0 ? vis32[x[k] >> 5] : ~0u;
+    for (int k = 0; k < K; ++k) w[k] = x[k] < 0 ? ~0u : (T.m_f < kPreloadMinEdges ? 0u : vis32[x[k] >> 5]);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const uint32_t bit = x[k] >= 0 ? 1u << (x[k] & 31) : 0u;
@@ -560,19 +575,11 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
   for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
     const bool has = j < deg;
     const int32_t v = has ? G.col[row0 + j] : 0;
-    td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, nfound, dfound);
+    td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
   }
 }
 
 
-// One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
-//   [0, nb_small)                 thread per vertex of degree <= t1;
-//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
-//                                 reading the row 64 neighbours at a time;
-//   the rest                      workgroup per t2-edge chunk of a larger
-//                                 vertex.
-// Ends with the staged queue entries flushed and the workgroup's counts in
-// `counts`.  All threads of the workgroup call it.
 // Wavefronts per medium vertex: as many as the role has per queued vertex,
 // at most one per kWave * kTdUnroll edges of the longest row it can hold:
 // a medium row (t2 edges at most) and no longer than the whole frontier's
@@ -588,6 +595,14 @@ __host__ __device__ inline int64_t medium_split(int64_t cnt, int64_t waves, int6
   return kpv < 1 ? 1 : kpv;
 }
 
+// One top-down level for workgroup `blk` of `nblk`.  Roles by workgroup:
+//   [0, nb_small)                 thread per vertex of degree <= t1;
+//   [nb_small, nb_small+nb_med)   wavefront per vertex of degree in (t1, t2],
+//                                 reading the row 64 neighbours at a time;
+//   the rest                      workgroup per t2-edge chunk of a larger
+//                                 vertex.
+// Ends with the staged queue entries flushed and the workgroup's counts in
+// `counts`.  All threads of the workgroup call it.
 template <class RowT>
 __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, const Stage &S, int blk,
                                          int nblk, int nb_small, int nb_med,
@@ -731,7 +746,7 @@ __device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLev
         const int64_t j = b + lane;
         const bool has = j < end;
         const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, T.level, T.dist, T.parent, fbm, has, ub, v, nfound, dfound);
+        td_visit(G, S, qn, T.level, T.dist, T.parent, fbm, has, ub, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
       }
     }
   };
