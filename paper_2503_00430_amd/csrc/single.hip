@@ -497,7 +497,12 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
   TdLevel t;
   t.qcur = c->qcur;
   t.level = c->level;
-  for (int b = 0; b < 3; ++b) t.cnt[b] = c->qcnt[t.qcur][b];
+  // both sets' counts are read together with the rest, then selected (no
+  // load that waits for qcur)
+  unsigned q[2][3];
+  for (int s = 0; s < 2; ++s)
+    for (int b = 0; b < 3; ++b) q[s][b] = c->qcnt[s][b];
+  for (int b = 0; b < 3; ++b) t.cnt[b] = t.qcur ? q[1][b] : q[0][b];
   t.m_f = c->m_f;
   t.dist = c->dist;
   t.parent = c->parent;
