@@ -855,12 +855,12 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   // the adds must have completed before this workgroup is counted
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   unsigned arrived = 0;
-  if (lane == 0) arrived = atomicAdd(&arrive[grp * kLineU32], 1u);
-  if (__shfl(arrived, 0) != gsize - 1) return;
-  if (lane == 0) {
-    atomicExch(&arrive[grp * kLineU32], 0u);
-    arrived = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u);
+  if (gsize > 1) {  // (a group of one workgroup goes straight to the top counter)
+    if (lane == 0) arrived = atomicAdd(&arrive[grp * kLineU32], 1u);
+    if (__shfl(arrived, 0) != gsize - 1) return;
+    if (lane == 0) atomicExch(&arrive[grp * kLineU32], 0u);
   }
+  if (lane == 0) arrived = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u);
   if (__shfl(arrived, 0) != ngroups - 1) return;
   if (lane == 0) atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
   // lane g * kPartials + k takes accumulator k of group g; sums over the
