@@ -313,14 +313,19 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
 
 // Level bookkeeping and the direction rule, applied by one thread to the
 // level's totals {found, degree sum of found, scanned, examined}.
-__device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&tot)[kPartials]) {
-  const int32_t L = c->level;
+// `bumped` >= 0: the caller has already stored level bumped + 1 and waited
+// for that store (it overlapped the caller's last round trip).
+__device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&tot)[kPartials],
+                             int32_t bumped = -1) {
+  const int32_t L = bumped >= 0 ? bumped : c->level;
   const int32_t cur = c->dir;
   // The level number changes first, and reaches the cache before any other
   // field changes: a workgroup of this level's launch that starts only now
   // reads the fields, then the number, and leaves when the number moved on.
-  c->level = L + 1;
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (bumped < 0) {
+    c->level = L + 1;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
   const int64_t found = (int64_t)tot[0];
   const int64_t fdeg = (int64_t)tot[1];
   if (L < c->rec_cap) {
@@ -806,10 +811,11 @@ enum LevelMode : int32_t {
 // All threads of the workgroup call it.
 
 // `rank` numbers the nactive workgroups that take part (workgroups with no
-// work in the level exit before and do not arrive).
+// work in the level exit before and do not arrive); `level` is the level
+// being run, or -1 (then the deciding thread reads it).
 template <int K, class RowT>
 __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, const unsigned long long (&v)[K],
-                                          unsigned rank, unsigned nactive) {
+                                          unsigned rank, unsigned nactive, int32_t level) {
   if (!(mode & kFusedDecide)) {
     block_partials<K>(G, v, rank);
     return;
@@ -819,6 +825,10 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   if (nactive == 1) {  // the only workgroup of the level: reduce in LDS and decide
     __shared__ unsigned long long one[K][16];
     const int w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {  // first (see decide_apply), overlapping the reduction
+      if (level < 0) level = G.ctl->level;
+      G.ctl->level = level + 1;
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const unsigned long long sum = wave_sum(v[k]);
@@ -829,7 +839,8 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
       unsigned long long tot[kPartials] = {0, 0, 0, 0};
       for (int k = 0; k < K; ++k)
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot[k] += one[k][i];
-      decide_apply(G.ctl, G.recs, tot);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      decide_apply(G.ctl, G.recs, tot, level);
     }
     return;
   }
@@ -862,7 +873,11 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   }
   if (lane == 0) arrived = atomicAdd(&arrive[kArriveGroups * kLineU32], 1u);
   if (__shfl(arrived, 0) != ngroups - 1) return;
-  if (lane == 0) atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
+  if (lane == 0) {
+    if (level < 0) level = G.ctl->level;
+    G.ctl->level = level + 1;  // first (see decide_apply); the exchange below waits for it
+    atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
+  }
   // lane g * kPartials + k takes accumulator k of group g; sums over the
   // lanes of equal k (lane mod kPartials) give the totals
   static_assert((kPartials & (kPartials - 1)) == 0 && kArriveGroups * kPartials <= kWave,
@@ -874,7 +889,8 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   unsigned long long tot[kPartials];
 #pragma unroll
   for (int k = 0; k < kPartials; ++k) tot[k] = __shfl(x, k);
-  if (lane == 0) decide_apply(G.ctl, G.recs, tot);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (lane == 0) decide_apply(G.ctl, G.recs, tot, level);
 }
 
 // Persistent top-down search (top-down-only policies): every level of the
@@ -1234,8 +1250,10 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
   extern __shared__ __align__(16) char lds[];
   unsigned long long counts[kPartials] = {0, 0, 0, 0};
   unsigned rank = blockIdx.x, nactive = gridDim.x;
+  int32_t level;
   if (D == kTD || (D == kAnyDir && dir == kTD)) {
     const TdLevel T = td_level_state(G, c);
+    level = T.level;
     if (!level_still(c, T.level, lvl_mod, lvl_rem)) return;
     if (T.from_bitmap) {  // every workgroup takes a share of the frontier words
       const Stage S = stage_open(lds);
@@ -1244,7 +1262,7 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
       td_level_bitmap(G, T, S, ring, tc);
       counts[0] = tc[0];
       counts[1] = tc[1];
-      end_level<kPartials>(G, mode, counts, rank, nactive);
+      end_level<kPartials>(G, mode, counts, rank, nactive, T.level);
       return;
     }
     // only the workgroups whose role has work this level take part
@@ -1267,15 +1285,16 @@ __global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_smal
     counts[0] = tc[0];
     counts[1] = tc[1];
   } else {
+    // (dir has been read and used above, so this load follows it; a
+    // bottom-up launch of the host loop has no workgroup that starts late)
+    level = -1;  // (the decide step reads it)
     if (D == kAnyDir) {
-      // (dir has been read and used above, so this load follows it; a
-      // bottom-up launch of the host loop has no workgroup that starts late)
-      const int32_t lv = __hip_atomic_load(&c->level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (lv % lvl_mod != lvl_rem) return;
+      level = __hip_atomic_load(&c->level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (level % lvl_mod != lvl_rem) return;
     }
     bu_level(G, c, lds, counts);
   }
-  end_level<kPartials>(G, mode, counts, rank, nactive);
+  end_level<kPartials>(G, mode, counts, rank, nactive, level);
 }
 
 // Head records: degree and the first three neighbours (-1 where the row is
