@@ -43,6 +43,7 @@ GRAPH_SPACE = {
     "graph_td_blocks": [16, 32, 64, 128, 256],
     "graph_chunk_levels": [8, 32, 128],
     "block_size": [256, 512, 1024],
+    "td_wave_degree": [4, 8, 16],
 }
 BATCH_SPACE = {
     "msbfs_bu_percent": [1, 2, 5, 10, 20, 50],
