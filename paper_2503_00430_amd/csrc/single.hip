@@ -5,38 +5,45 @@
 // level runs in one of two directions (Section 2, BFS-Hybrid):
 //   top-down  - every frontier vertex examines its neighbours; a neighbour
 //               whose visited bit is clear is claimed with one atomicOr on
-//               its 64-bit visited word, and the winner stores dist and
-//               parent with plain stores (Section 2, BFS-NonAtomic: no
-//               atomic on the distance) and appends the vertex to the next
-//               frontier queue;
+//               its visited word, and the winner stores dist and parent
+//               with plain stores (Section 2, BFS-NonAtomic: no atomic on
+//               the distance) and appends the vertex to the next frontier
+//               queue;
 //   bottom-up - every unvisited vertex scans its own row for a neighbour in
 //               the frontier bitmap and stops at the first hit (Section 2,
 //               Listing 2).
 // Visited state lives in a bitmap (Section 2, BFS-VisitedBitmap).  A bit of
 // a packed bitmap is never set with a plain read-modify-write from two
 // threads: top-down uses atomicOr, bottom-up gives each 64-vertex word to
-// one wavefront, which alone writes it.
+// one wavefront, which alone writes it.  (For the paper's ablation the
+// top-down claim can instead be a compare-and-swap on the distance or a
+// plain test and store: bfs_params.td_visited.)
 //
-// Mapping onto CDNA4 (wave64):
-//   * top-down work is split by degree: one thread per vertex of degree
-//     <= t1, one wavefront per vertex of degree in (t1, t2], and one
-//     workgroup per t2-edge chunk of larger vertices, so neighbour ids are
-//     read from HBM in coalesced runs and hubs do not serialise a wave;
-//   * discoveries are appended with one atomicAdd per wavefront and bucket
-//     (ballot + mbcnt give each lane its slot);
-//   * bottom-up gives a wavefront one 64-bit visited word (64 consecutive
-//     vertices): rows of degree <= tbu are scanned by their own lane, longer
-//     rows by the whole wavefront 64 neighbours at a time with a ballot
-//     early exit; the found mask is written by lane 0 as the next-frontier
-//     word and OR-ed into the visited word;
-//   * frontier counts and degree sums are reduced per workgroup and added to
-//     the device control block, where a single-thread kernel applies the
-//     direction rule (Section 2: alpha/beta of BFS-Hybrid dagger, or the 5 %
-//     frontier rule of BFS-Hybrid; Section 3: top-down only below average
-//     degree 7) and converts the frontier between queue and bitmap form when
-//     the direction changes.
+// Mapping onto CDNA4 (wave64), one kernel launch per level (k_level):
+//   * top-down work is split by degree into roles of one launch: a thread
+//     per vertex of degree <= t1, a wavefront (or, for few long rows,
+//     several) per vertex of degree in (t1, t2], a workgroup per t2-edge
+//     chunk of larger vertices; discoveries are staged in LDS per degree
+//     class (ballot + mbcnt slots) and copied out with one global atomicAdd
+//     per workgroup and class;
+//   * bottom-up gives each wavefront a run of 64 visited words, compacts
+//     their unvisited vertices into batches of 64 candidates, tests the
+//     first neighbours from a 16-byte head record per vertex and scans the
+//     rest of the rows that miss 64 at a time; the found masks become the
+//     next-frontier and visited words with one coalesced store per run;
+//   * hybrid searches keep the frontier bitmap exact during top-down levels
+//     (set on discovery, cleared on expansion), and the top-down level after
+//     a bottom-up phase reads its frontier from that bitmap, so no level
+//     converts between queue and bitmap form;
+//   * the level's counts are reduced by the level kernel itself: the last
+//     workgroup to arrive applies the direction rule (Section 2: alpha/beta
+//     of BFS-Hybrid dagger, or the 5 % frontier rule of BFS-Hybrid; Section
+//     3: top-down only below average degree 7) and advances the control
+//     block.
 // Every kernel reads the level state from the control block, so the same
-// kernels serve a host-driven loop and a captured hipGraph of many levels.
+// kernel serves a host-driven loop, a queued loop and a captured hipGraph of
+// many levels; each launch checks that the level it reads is the one it was
+// made for.
 
 #include <algorithm>
 #include <chrono>
