@@ -25,8 +25,8 @@
 //             frontier);
 //   finalize  touched vertices: new lanes become seen and frontier, their
 //             distances are written, the vertex joins the next frontier
-//             queue;
-//   decide    reduce the level's counts, pick the next direction.
+//             queue; the last workgroup reduces the level's counts and picks
+//             the next direction (the decide step).
 // Top-down levels touch only the frontier and its edges, so large-diameter
 // graphs cost per level what their frontier costs.
 
@@ -393,17 +393,34 @@ __global__ void k_sv_expand(SvArgs<RowT> A) {
 }
 
 // Touched vertices become the new frontier.
+// Accumulators of the level's totals (new lane pairs, frontier edges, OR of
+// the new lanes) per group of workgroups, then the groups' arrival counters
+// and the counter over the groups, each in its own 128-byte line of the
+// batch's partials array.
+constexpr int kSvGroups = 8;
+constexpr int kSvLine = 16;  // 64-bit words per 128-byte line
+constexpr size_t kSvArriveOffset = (size_t)kSvGroups * 3 * kSvLine;
+static_assert(kSvArriveOffset + (kSvGroups + 1) * kSvLine <= (size_t)kSvMaxBlocks * 3,
+              "the partials array holds the accumulators and counters");
+
+// Touched vertices become the new frontier; the last workgroup to finish
+// then reduces the level's totals and applies the decide step (lanes whose
+// frontier emptied finish, the direction of the next level).  Only the
+// workgroups that have touched entries take part, and workgroup 0 always
+// does, so no workgroup can start after the decide step and act on the next
+// level (the reset touched count makes every workgroup but 0 idle).
 template <class RowT>
 __global__ void k_sv_finalize(SvArgs<RowT> A) {
-  const ServeCtl *c = A.ctl;
+  ServeCtl *c = A.ctl;
   if (!c->alive) return;
+  const int64_t nt = c->tcnt;
+  const int64_t nact = max((int64_t)1, min((int64_t)gridDim.x, (nt + blockDim.x - 1) / blockDim.x));
+  if ((int64_t)blockIdx.x >= nact) return;  // uniform: no touched entry for this workgroup
   extern __shared__ __align__(16) char lds[];
   const Stage1 S = stage1_open(lds);
-  ServeCtl *cw = A.ctl;
   const int nsel = c->fsel ^ 1;
   int32_t *fq_next = nsel ? A.fq[1] : A.fq[0];
-  unsigned *fcnt_next = &cw->fcnt[nsel];
-  const int64_t nt = c->tcnt;
+  unsigned *fcnt_next = &c->fcnt[nsel];
   const int32_t level = c->level;
   unsigned long long pairs = 0, fedges = 0, bits = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -423,7 +440,7 @@ __global__ void k_sv_finalize(SvArgs<RowT> A) {
         pairs += (unsigned long long)__popcll(nb);
         const int64_t deg = (int64_t)A.rp[x + 1] - (int64_t)A.rp[x];
         fedges += (unsigned long long)deg;
-        if (deg > kSvChunk) push_chunks(A, cw, nsel, x, deg);
+        if (deg > kSvChunk) push_chunks(A, c, nsel, x, deg);
         bits |= nb;
         uint64_t b = nb;
         while (b) {
@@ -446,54 +463,46 @@ __global__ void k_sv_finalize(SvArgs<RowT> A) {
     part[2][threadIdx.x >> 6] = bits;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long p = 0, fe = 0, b = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      p += part[0][w];
-      fe += part[1][w];
-      b |= part[2][w];
-    }
-    A.partials[(size_t)blockIdx.x * 3 + 0] = p;
-    A.partials[(size_t)blockIdx.x * 3 + 1] = fe;
-    A.partials[(size_t)blockIdx.x * 3 + 2] = b;
+  if (threadIdx.x >= kWave) return;  // wave 0 finishes
+  const int lane = threadIdx.x;
+  unsigned long long t = 0;
+  if (lane < 3)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = lane == 2 ? (t | part[2][w]) : t + part[lane][w];
+  unsigned long long *acc = A.partials;
+  unsigned long long *arrive = A.partials + kSvArriveOffset;
+  const unsigned grp = blockIdx.x % kSvGroups;
+  const unsigned na = (unsigned)nact;
+  const unsigned gsize = (na - grp + kSvGroups - 1) / kSvGroups;
+  const unsigned ngroups = na < (unsigned)kSvGroups ? na : (unsigned)kSvGroups;
+  if (lane < 3 && t) {
+    unsigned long long *a = acc + ((size_t)grp * 3 + lane) * kSvLine;
+    if (lane == 2) atomicOr(a, t);
+    else atomicAdd(a, t);
   }
-}
-
-template <class RowT>
-__global__ void __launch_bounds__(1024) k_sv_decide(SvArgs<RowT> A, int32_t nblocks) {
-  ServeCtl *c = A.ctl;
-  if (!c->alive) return;
-  __shared__ unsigned long long red[3][16];
-  unsigned long long p = 0, fe = 0, b = 0;
-  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
-    p += A.partials[(size_t)i * 3 + 0];
-    fe += A.partials[(size_t)i * 3 + 1];
-    b |= A.partials[(size_t)i * 3 + 2];
-    A.partials[(size_t)i * 3 + 0] = 0;
-    A.partials[(size_t)i * 3 + 1] = 0;
-    A.partials[(size_t)i * 3 + 2] = 0;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the adds complete before the arrival
+  unsigned long long arrived = 0;
+  if (gsize > 1) {
+    if (lane == 0) arrived = atomicAdd(arrive + (size_t)grp * kSvLine, 1ull);
+    if (__shfl(arrived, 0) != gsize - 1) return;
+    if (lane == 0) atomicExch(arrive + (size_t)grp * kSvLine, 0ull);
   }
-  p = wave_sum(p);
-  fe = wave_sum(fe);
-  b = wave_or(b);
-  if (lane_id() == 0) {
-    red[0][threadIdx.x >> 6] = p;
-    red[1][threadIdx.x >> 6] = fe;
-    red[2][threadIdx.x >> 6] = b;
+  if (lane == 0) arrived = atomicAdd(arrive + (size_t)kSvGroups * kSvLine, 1ull);
+  if (__shfl(arrived, 0) != ngroups - 1) return;
+  if (lane == 0) atomicExch(arrive + (size_t)kSvGroups * kSvLine, 0ull);
+  // lane g * 3 + k takes accumulator k of group g
+  unsigned long long x = 0;
+  if ((unsigned)lane < ngroups * 3) x = atomicExch(acc + (size_t)lane * kSvLine, 0ull);
+  unsigned long long tf = 0, tb = 0;
+  for (unsigned g = 0; g < ngroups; ++g) {
+    tf += __shfl(x, (int)(g * 3 + 1));
+    tb |= __shfl(x, (int)(g * 3 + 2));
   }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  unsigned long long tp = 0, tf = 0, tb = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    tp += red[0][w];
-    tf += red[1][w];
-    tb |= red[2][w];
-  }
+  if (lane != 0) return;
   uint64_t ended = c->alive & ~tb;  // lanes whose new frontier is empty
   while (ended) {
     const int i = __ffsll((unsigned long long)ended) - 1;
     ended &= ended - 1;
-    c->finish[i] = c->level + 1;
+    c->finish[i] = level + 1;
   }
   c->alive = tb;
   c->pcnt = c->fcnt[c->fsel];
@@ -501,10 +510,9 @@ __global__ void __launch_bounds__(1024) k_sv_decide(SvArgs<RowT> A, int32_t nblo
   c->hcnt[c->fsel] = 0;
   c->fsel ^= 1;
   c->tcnt = 0;
-  c->level += 1;
+  c->level = level + 1;
   c->levels_run += 1;
   c->dir = (tf * 100ull > (unsigned long long)c->bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
-  (void)tp;
 }
 
 // ---------------------------------------------------------------------------
@@ -658,7 +666,6 @@ int issue_chunk(Batch *b, int levels) {
   for (int l = 0; l < levels; ++l) {
     hipLaunchKernelGGL(k_sv_expand<RowT>, dim3(nblocks), dim3(bs), lds, st, A);
     hipLaunchKernelGGL(k_sv_finalize<RowT>, dim3(nblocks), dim3(bs), lds, st, A);
-    hipLaunchKernelGGL(k_sv_decide<RowT>, dim3(1), dim3(1024), 0, st, A, nblocks);
   }
   BFS_HIP(hipGetLastError());
   BFS_HIP(hipMemcpyAsync(b->mirror, b->ctl, sizeof(ServeCtl), hipMemcpyDeviceToHost, st));
