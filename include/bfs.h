@@ -127,7 +127,9 @@ typedef struct bfs_params {
                                  scanned by the whole wavefront (default 2048) */
   int32_t block_size;         /* threads per workgroup of the level kernels (default 512) */
   int32_t loop;               /* bfs_loop */
-  int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 8) */
+  int32_t graph_chunk_levels; /* GRAPH loop: levels per captured graph (default 8; 1 runs
+                                 as 2, since each launch checks its level modulo
+                                 the chunk length) */
   int32_t collect_timing;     /* nonzero: time each level with HIP events (HOST and QUEUED loops) */
   int32_t msbfs_block_size;   /* batched search: threads per workgroup (default 256) */
   int32_t msbfs_bu_percent;   /* batched search: a level runs bottom-up when its frontier
