@@ -112,6 +112,8 @@ struct DevG {
 struct MsScratch {
   uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
   unsigned long long *counters = nullptr;
+  uint64_t *hq = nullptr;  // chunk queue of long top-down rows
+  int64_t hq_cap = 0;
   int64_t words = 0;
   size_t bytes = 0;
 };

@@ -40,6 +40,7 @@ struct MsCtl {
   int32_t pad;
   unsigned long long alive;  // searches whose frontier is not empty
   int32_t src[64];
+  unsigned long long hcnt;   // chunk entries of the running top-down level's long rows
 };
 
 constexpr size_t kMsCtlBytes = 1024;  // MsCtl, rounded up
@@ -59,7 +60,15 @@ struct MsArgs {
   int32_t bu_percent;
   int32_t heavy;  // rows longer than this are handled by the whole wavefront
   int32_t aligned4;  // dist8 is 4-byte aligned
+  uint64_t *hq;      // chunk queue of the rows longer than kMsChunk: chunk << 32 | v
+  int64_t hq_cap;
 };
+
+// Top-down rows longer than kMsChunk edges are not walked by the wavefront
+// that owns their vertex (a hub's row would take one dependent step per 64
+// edges): their kMsChunk-edge chunks are queued and, after a grid barrier,
+// spread over every wavefront.
+constexpr int64_t kMsChunk = 1024;
 
 // Top-down expansion of the wavefront's 64 vertices starting at v0.
 template <class RowT>
@@ -71,6 +80,13 @@ __device__ void ms_td(const MsArgs<RowT> &A, int64_t v0) {
   if (f) {
     beg = (int64_t)A.rp[v];
     end = (int64_t)A.rp[v + 1];
+  }
+  if (f && end - beg > kMsChunk) {  // a long row: queue its chunks for every wavefront
+    const uint64_t nch = (uint64_t)((end - beg + kMsChunk - 1) / kMsChunk);
+    const unsigned long long base = atomicAdd(&A.ctl->hcnt, (unsigned long long)nch);
+    for (uint64_t k = 0; k < nch; ++k)
+      if ((int64_t)(base + k) < A.hq_cap) A.hq[base + k] = (k << 32) | (uint32_t)v;
+    beg = end = 0;
   }
   const bool heavy = (end - beg) > A.heavy;
   if (f && !heavy) {
@@ -160,6 +176,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     c->dir = 0;
     c->done = 0;
     c->levels = 0;
+    c->hcnt = 0;
     c->alive = A.k == 64 ? ~0ull : ((1ull << A.k) - 1);
   }
   grid.sync();
@@ -180,6 +197,22 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
         ms_td(A, w * kWave);
       else
         ms_bu(A, w * kWave, alive);
+    }
+    if (dir == 0) {  // the long rows' chunks, one per wavefront
+      grid.sync();
+      const int64_t nh = min((int64_t)__atomic_load_n(&c->hcnt, __ATOMIC_RELAXED), A.hq_cap);
+      for (int64_t i = wave; i < nh; i += nwaves) {
+        const uint64_t e = A.hq[i];
+        const int32_t v = (int32_t)(uint32_t)e;
+        const uint64_t f = A.front[v];
+        const int64_t b0 = (int64_t)A.rp[v] + (int64_t)(e >> 32) * kMsChunk;
+        const int64_t e0 = min((int64_t)A.rp[v + 1], b0 + kMsChunk);
+        for (int64_t j = b0 + lane; j < e0; j += kWave) {
+          const int32_t x = A.col[j];
+          const uint64_t nb = f & ~A.seen[x];
+          if (nb) atomicOr(reinterpret_cast<unsigned long long *>(A.next + x), (unsigned long long)nb);
+        }
+      }
     }
     grid.sync();
     // Finalize: next -> new frontier, seen, distance rows.
@@ -253,6 +286,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
           tb |= part[2][i];
         }
         c->alive = tb;
+        c->hcnt = 0;
         c->levels = (int32_t)(level + 1);
         if (tp == 0)
           c->done = 1;
@@ -268,9 +302,13 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
 int ensure_ms_scratch(bfs_graph *g) {
   if (g->ms.seen) return BFS_OK;
   const size_t words = (size_t)g->n;
-  void *p[4] = {nullptr, nullptr, nullptr, nullptr};
-  const size_t sizes[4] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8};
-  for (int i = 0; i < 4; ++i) {
+  // every queued row has more than kMsChunk edges and enters a level's
+  // frontier once, so a level has fewer than 2 nnz / kMsChunk chunks
+  const int64_t hq_cap = 2 * (g->nnz / kMsChunk) + 64;
+  void *p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t sizes[5] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8,
+                           (size_t)hq_cap * 8};
+  for (int i = 0; i < 5; ++i) {
     if (hipMalloc(&p[i], sizes[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
       return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate batched-search scratch");
@@ -280,7 +318,9 @@ int ensure_ms_scratch(bfs_graph *g) {
   g->ms.front = static_cast<uint64_t *>(p[1]);
   g->ms.next = static_cast<uint64_t *>(p[2]);
   g->ms.counters = static_cast<unsigned long long *>(p[3]);
-  g->ms.bytes = sizes[0] + sizes[1] + sizes[2] + sizes[3];
+  g->ms.hq = static_cast<uint64_t *>(p[4]);
+  g->ms.hq_cap = hq_cap;
+  g->ms.bytes = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4];
   return BFS_OK;
 }
 
@@ -297,6 +337,8 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   A.front = g->ms.front;
   A.next = g->ms.next;
   A.dist8 = dist8;
+  A.hq = g->ms.hq;
+  A.hq_cap = g->ms.hq_cap;
   A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
   A.partials = g->ms.counters + kMsCtlBytes / 8;
   A.k = k;
