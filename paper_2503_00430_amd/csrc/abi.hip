@@ -133,7 +133,7 @@ static void destroy(bfs_graph *g) {
   release_graph_exec(g);
   void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->headc, g->hrank, g->vis, g->bm[0], g->bm[1], g->qs[0], g->qs[1],
                   g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->slot, g->ctl, g->recs, g->partials,
-                  g->ms.seen, g->ms.front, g->ms.next, g->ms.counters, g->ms.hq};
+                  g->ms.seen, g->ms.front, g->ms.next, g->ms.counters, g->ms.hq, g->ms.planes};
   for (void *p : ptrs) free_dev(p);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   if (g->ev_start) (void)hipEventDestroy(g->ev_start);

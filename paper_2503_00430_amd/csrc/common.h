@@ -114,6 +114,7 @@ struct MsScratch {
   unsigned long long *counters = nullptr;
   uint64_t *hq = nullptr;  // chunk queue of long top-down rows
   int64_t hq_cap = 0;
+  uint64_t *planes = nullptr;  // 8 bit planes of the distances, [8][n]
   int64_t words = 0;
   size_t bytes = 0;
 };

@@ -12,9 +12,15 @@
 //               its neighbours, stopping as soon as every search it still
 //               lacks has been found (the early exit of Section 2,
 //               BFS-Hybrid, extended to 64 searches);
-// then a finalize pass turns next into the new frontier, marks it seen and
-// writes the level into the uint8 distance rows.  The direction of each
-// level follows the frontier's edge count.
+// then a finalize pass turns next into the new frontier and marks it seen.
+// The direction of each level follows the frontier's edge count.
+//
+// Distances.  A small batch writes each level into the uint8 distance rows
+// as it is found.  Those stores fill 64-byte row segments only in part, one
+// per search and level, so a batch of kMsPlaneMinK or more searches instead
+// keeps the distances as 8 bit planes per vertex (bit i of plane b is bit b
+// of search i's distance) and writes the rows once, in whole segments, after
+// the last level.
 //
 // The whole search is one cooperative launch: levels are separated by
 // grid-wide barriers, and a single thread decides the next direction and
@@ -62,7 +68,37 @@ struct MsArgs {
   int32_t aligned4;  // dist8 is 4-byte aligned
   uint64_t *hq;      // chunk queue of the rows longer than kMsChunk: chunk << 32 | v
   int64_t hq_cap;
+  uint64_t *planes;  // [8][n] distance bit planes, or null: rows written per level
 };
+
+constexpr int kMsPlaneMinK = 16;
+
+// Distance rows from the bit planes: lane = vertex v, one byte store per
+// search, so a wavefront writes whole 64-byte row segments.  dmax is the
+// largest distance written; plane b was written iff 2^b <= dmax, and NP
+// planes cover dmax (NP = 8 also covers the saturated 255).
+template <int NP, class RowT>
+__device__ void ms_write_rows(const MsArgs<RowT> &A, int64_t v, int dmax) {
+  const uint64_t s = A.seen[v];
+  uint32_t lo[NP], hi[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    const uint64_t p = (1 << b) <= dmax ? A.planes[(int64_t)b * A.n + v] : 0ull;
+    lo[b] = (uint32_t)p;
+    hi[b] = (uint32_t)(p >> 32);
+  }
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    if (i >= A.k) break;
+    const uint32_t *q = i < 32 ? lo : hi;
+    const int sh = i & 31;
+    uint32_t d = 0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) d |= ((q[b] >> sh) & 1u) << b;
+    const uint8_t byte = ((s >> i) & 1ull) ? (uint8_t)d : (uint8_t)255;
+    __builtin_nontemporal_store(byte, A.dist8 + (int64_t)i * A.n + v);
+  }
+}
 
 // Top-down rows longer than kMsChunk edges are not walked by the wavefront
 // that owns their vertex (a hub's row would take one dependent step per 64
@@ -170,8 +206,10 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   uint32_t *d32 = reinterpret_cast<uint32_t *>(A.dist8);
   // (streaming stores: the rows are written once more, byte by byte, and
   // never read here)
-  for (int64_t i = tid; i < head; i += nthreads) __builtin_nontemporal_store(0xFFFFFFFFu, d32 + i);
-  for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) __builtin_nontemporal_store((uint8_t)255, A.dist8 + i);
+  if (!A.planes) {
+    for (int64_t i = tid; i < head; i += nthreads) __builtin_nontemporal_store(0xFFFFFFFFu, d32 + i);
+    for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) __builtin_nontemporal_store((uint8_t)255, A.dist8 + i);
+  }
   if (tid == 0) {
     c->dir = 0;
     c->done = 0;
@@ -185,7 +223,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     const unsigned long long bit = 1ull << tid;
     atomicOr(reinterpret_cast<unsigned long long *>(A.seen + s), bit);
     atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
-    A.dist8[(int64_t)tid * A.n + s] = 0;
+    if (!A.planes) A.dist8[(int64_t)tid * A.n + s] = 0;
   }
   grid.sync();
 
@@ -217,6 +255,8 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     grid.sync();
     // Finalize: next -> new frontier, seen, distance rows.
     const uint8_t dval = (uint8_t)(level + 1 < 255 ? level + 1 : 255);
+    // planes: the first level whose distance sets bit b writes plane b in
+    // full (so no plane is cleared beforehand); later ones OR into it
     unsigned long long pairs = 0, fedges = 0, bits = 0;
     for (int64_t w = wave; w < nwords; w += nwaves) {
       const int64_t v = w * kWave + lane;
@@ -232,7 +272,18 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
           fedges += (unsigned long long)((int64_t)A.rp[v + 1] - (int64_t)A.rp[v]);
           bits |= nb;
         }
+        if (A.planes) {
+          for (int b = 0; b < 8; ++b) {
+            if (!((dval >> b) & 1)) continue;
+            uint64_t *pb = A.planes + (int64_t)b * A.n + v;
+            if (dval == (1u << b))
+              *pb = nb;
+            else if (nb)
+              *pb |= nb;
+          }
+        }
       }
+      if (A.planes) continue;
       uint64_t any = wave_or(nb);
       while (any) {  // one coalesced byte row segment per search that advanced
         const int i = __ffsll((unsigned long long)any) - 1;
@@ -297,6 +348,17 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     grid.sync();
     if (__atomic_load_n(&c->done, __ATOMIC_RELAXED)) break;
   }
+  if (A.planes) {
+    // the last level's distance bounds every distance; planes up to its top
+    // bit were written
+    const int dmax = min(__atomic_load_n(&c->levels, __ATOMIC_RELAXED), 255);
+    for (int64_t v = tid; v < A.n; v += nthreads) {
+      if (dmax < 16)
+        ms_write_rows<4>(A, v, dmax);
+      else
+        ms_write_rows<8>(A, v, dmax);
+    }
+  }
 }
 
 int ensure_ms_scratch(bfs_graph *g) {
@@ -305,10 +367,10 @@ int ensure_ms_scratch(bfs_graph *g) {
   // every queued row has more than kMsChunk edges and enters a level's
   // frontier once, so a level has fewer than 2 nnz / kMsChunk chunks
   const int64_t hq_cap = 2 * (g->nnz / kMsChunk) + 64;
-  void *p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  const size_t sizes[5] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8,
-                           (size_t)hq_cap * 8};
-  for (int i = 0; i < 5; ++i) {
+  void *p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t sizes[6] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8,
+                           (size_t)hq_cap * 8, 8 * words * 8};
+  for (int i = 0; i < 6; ++i) {
     if (hipMalloc(&p[i], sizes[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
       return fail(BFS_ERR_OUT_OF_MEMORY, "cannot allocate batched-search scratch");
@@ -320,7 +382,8 @@ int ensure_ms_scratch(bfs_graph *g) {
   g->ms.counters = static_cast<unsigned long long *>(p[3]);
   g->ms.hq = static_cast<uint64_t *>(p[4]);
   g->ms.hq_cap = hq_cap;
-  g->ms.bytes = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4];
+  g->ms.planes = static_cast<uint64_t *>(p[5]);
+  g->ms.bytes = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4] + sizes[5];
   return BFS_OK;
 }
 
@@ -339,6 +402,7 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   A.dist8 = dist8;
   A.hq = g->ms.hq;
   A.hq_cap = g->ms.hq_cap;
+  A.planes = k >= kMsPlaneMinK ? g->ms.planes : nullptr;
   A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
   A.partials = g->ms.counters + kMsCtlBytes / 8;
   A.k = k;

@@ -76,6 +76,40 @@ def test_saturation_long_path(bfs):
     gh.close()
 
 
+@pytest.mark.parametrize("n", [15, 16, 17, 40, 700])
+def test_bit_planes_on_paths(bfs, n):
+    """Batches of 16 or more searches keep their distances as bit planes
+    and write the rows after the last level: paths whose largest distance
+    needs 4 planes, exactly 5, more, and the saturated 255."""
+    say("batch bit planes path", n)
+    g, _ = graphs.path(n)
+    gh = upload(g)
+    srcs = ([0, n - 1] * 8 + list(range(0, n, max(1, n // 8))))[:24]
+    for k in (15, 16, len(srcs)):
+        np.testing.assert_array_equal(run_batch(bfs, gh, srcs[:k]), expect(g, srcs[:k]))
+    gh.close()
+
+
+def test_bit_planes_repeats_isolated_hubs(bfs):
+    say("batch bit planes: repeats, isolated, hub rows")
+    g = graphgen.from_edges(200, np.concatenate([np.arange(99), 100 + np.arange(80)]),
+                            np.concatenate([np.arange(1, 100), 101 + np.arange(80)]))
+    gh = upload(g)
+    srcs = [0, 0, 50, 199, 150, 99, 100, 180, 50] * 3  # repeats; 199 isolated
+    np.testing.assert_array_equal(run_batch(bfs, gh, srcs), expect(g, srcs))
+    gh.close()
+    k = 20000
+    u = np.concatenate([np.zeros(k, np.int64), np.arange(1, 300), [5000] * 3000])
+    v = np.concatenate([np.arange(1, k + 1), np.arange(2, 301), np.arange(10000, 13000)])
+    g = graphgen.from_edges(k + 1, u, v)
+    gh = upload(g)
+    srcs = [0, 1, 150, 5000, 12000, k, 7, 299, 300, 301, 9999, 10000, 10001, 13000, 13001, 42, 0]
+    for pct in (0, 100):
+        bfs.bfs_set_params(gh, msbfs_bu_percent=pct)
+        np.testing.assert_array_equal(run_batch(bfs, gh, srcs), expect(g, srcs))
+    gh.close()
+
+
 def test_closed_forms(bfs):
     for name, mk in sorted(graphs.CLOSED_FORMS.items()):
         g, f = mk()
