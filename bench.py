@@ -404,6 +404,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, mesh and serving sections")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched section (RMAT-22, 64 sources), e.g. to profile its kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -429,6 +431,9 @@ def main():
     from paper_2503_00430_amd import autotune
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(bfs, torch)}), flush=True)
+        return
 
     t0 = time.time()
     g, sources, rp32 = make_graph(args.workload)
