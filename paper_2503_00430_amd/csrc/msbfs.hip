@@ -23,8 +23,9 @@
 // the last level.
 //
 // The whole search is one cooperative launch: levels are separated by
-// grid-wide barriers, and a single thread decides the next direction and
-// termination from counters reduced on the device.
+// grid-wide barriers.  Each workgroup adds its level totals into device
+// accumulators with atomics; after one barrier every workgroup reads them
+// and takes the same decision on the next direction and on termination.
 
 #include <hip/hip_cooperative_groups.h>
 
@@ -39,14 +40,18 @@ namespace bfsmi {
 namespace {
 
 // Device control block of one batched search.
+// Every workgroup takes the same per-level decision from the level's totals,
+// so none is published here; the totals of level L are accumulated into
+// acc[L % 3] (one 128-byte line each), and level L's decide clears
+// acc[(L + 2) % 3], whose last readers passed a grid barrier before and whose
+// next writers come after another.  hcnt[L & 1] counts level L's chunk
+// entries and is cleared in the same way by level L's decide.
 struct MsCtl {
-  int32_t dir;    // 0 top-down, 1 bottom-up
-  int32_t done;
-  int32_t levels;
+  int32_t levels;  // levels run (for the caller; the kernel keeps its own count)
   int32_t pad;
-  unsigned long long alive;  // searches whose frontier is not empty
   int32_t src[64];
-  unsigned long long hcnt;   // chunk entries of the running top-down level's long rows
+  unsigned long long hcnt[2];
+  alignas(128) unsigned long long acc[3][16];  // [0] new pairs, [1] frontier edges, [2] OR of new bits
 };
 
 constexpr size_t kMsCtlBytes = 1024;  // MsCtl, rounded up
@@ -61,7 +66,6 @@ struct MsArgs {
   uint64_t *seen, *front, *next;
   uint8_t *dist8;
   MsCtl *ctl;
-  unsigned long long *partials;  // [grid][3]: new pairs, frontier edges, OR of new bits
   int32_t k;
   int32_t bu_percent;
   int32_t heavy;  // rows longer than this are handled by the whole wavefront
@@ -108,7 +112,7 @@ constexpr int64_t kMsChunk = 1024;
 
 // Top-down expansion of the wavefront's 64 vertices starting at v0.
 template <class RowT>
-__device__ void ms_td(const MsArgs<RowT> &A, int64_t v0) {
+__device__ void ms_td(const MsArgs<RowT> &A, int64_t v0, unsigned long long *hcnt) {
   const int lane = lane_id();
   const int64_t v = v0 + lane;
   const uint64_t f = v < A.n ? A.front[v] : 0ull;
@@ -119,7 +123,7 @@ __device__ void ms_td(const MsArgs<RowT> &A, int64_t v0) {
   }
   if (f && end - beg > kMsChunk) {  // a long row: queue its chunks for every wavefront
     const uint64_t nch = (uint64_t)((end - beg + kMsChunk - 1) / kMsChunk);
-    const unsigned long long base = atomicAdd(&A.ctl->hcnt, (unsigned long long)nch);
+    const unsigned long long base = atomicAdd(hcnt, (unsigned long long)nch);
     for (uint64_t k = 0; k < nch; ++k)
       if ((int64_t)(base + k) < A.hq_cap) A.hq[base + k] = (k << 32) | (uint32_t)v;
     beg = end = 0;
@@ -211,11 +215,9 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     for (int64_t i = head * 4 + tid; i < bytes; i += nthreads) __builtin_nontemporal_store((uint8_t)255, A.dist8 + i);
   }
   if (tid == 0) {
-    c->dir = 0;
-    c->done = 0;
     c->levels = 0;
-    c->hcnt = 0;
-    c->alive = A.k == 64 ? ~0ull : ((1ull << A.k) - 1);
+    c->hcnt[0] = c->hcnt[1] = 0;
+    for (int i = 0; i < 3; ++i) c->acc[i][0] = c->acc[i][1] = c->acc[i][2] = 0;
   }
   grid.sync();
   if (tid < A.k) {
@@ -227,18 +229,20 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   }
   grid.sync();
 
+  int32_t dir = 0;  // 0 top-down, 1 bottom-up
+  uint64_t alive = A.k == 64 ? ~0ull : ((1ull << A.k) - 1);  // searches whose frontier is not empty
+  int dmax = (int)min(A.n + 1, (int64_t)255);                 // largest distance written
   for (int64_t level = 0; level <= A.n; ++level) {
-    const int32_t dir = __atomic_load_n(&c->dir, __ATOMIC_RELAXED);
-    const uint64_t alive = __atomic_load_n(&c->alive, __ATOMIC_RELAXED);
+    unsigned long long *hcnt = &c->hcnt[level & 1];
     for (int64_t w = wave; w < nwords; w += nwaves) {
       if (dir == 0)
-        ms_td(A, w * kWave);
+        ms_td(A, w * kWave, hcnt);
       else
         ms_bu(A, w * kWave, alive);
     }
     if (dir == 0) {  // the long rows' chunks, one per wavefront
       grid.sync();
-      const int64_t nh = min((int64_t)__atomic_load_n(&c->hcnt, __ATOMIC_RELAXED), A.hq_cap);
+      const int64_t nh = min((int64_t)__atomic_load_n(hcnt, __ATOMIC_RELAXED), A.hq_cap);
       for (int64_t i = wave; i < nh; i += nwaves) {
         const uint64_t e = A.hq[i];
         const int32_t v = (int32_t)(uint32_t)e;
@@ -300,58 +304,40 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
       part[2][threadIdx.x >> 6] = bits;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {  // this workgroup's totals, in its own slot
+    unsigned long long *acc = c->acc[level % 3];
+    if (threadIdx.x == 0) {  // this workgroup's totals into the level's accumulators
       unsigned long long p = 0, fe = 0, b = 0;
       for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
         p += part[0][i];
         fe += part[1][i];
         b |= part[2][i];
       }
-      A.partials[(size_t)blockIdx.x * 3 + 0] = p;
-      A.partials[(size_t)blockIdx.x * 3 + 1] = fe;
-      A.partials[(size_t)blockIdx.x * 3 + 2] = b;
-    }
-    grid.sync();
-    if (blockIdx.x == 0) {  // workgroup 0 reduces the slots and decides
-      unsigned long long p = 0, fe = 0, b = 0;
-      for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-        p += A.partials[(size_t)i * 3 + 0];
-        fe += A.partials[(size_t)i * 3 + 1];
-        b |= A.partials[(size_t)i * 3 + 2];
-      }
-      p = wave_sum(p);
-      fe = wave_sum(fe);
-      b = wave_or(b);
-      __syncthreads();  // `part` is reused
-      if (lane == 0) {
-        part[0][threadIdx.x >> 6] = p;
-        part[1][threadIdx.x >> 6] = fe;
-        part[2][threadIdx.x >> 6] = b;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        unsigned long long tp = 0, tf = 0, tb = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-          tp += part[0][i];
-          tf += part[1][i];
-          tb |= part[2][i];
-        }
-        c->alive = tb;
-        c->hcnt = 0;
-        c->levels = (int32_t)(level + 1);
-        if (tp == 0)
-          c->done = 1;
-        else
-          c->dir = (tf * 100ull > (unsigned long long)A.bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
+      if (p) {
+        atomicAdd(&acc[0], p);
+        atomicAdd(&acc[1], fe);
+        atomicOr(&acc[2], b);
       }
     }
     grid.sync();
-    if (__atomic_load_n(&c->done, __ATOMIC_RELAXED)) break;
+    const unsigned long long tp = __atomic_load_n(&acc[0], __ATOMIC_RELAXED);
+    const unsigned long long tf = __atomic_load_n(&acc[1], __ATOMIC_RELAXED);
+    const unsigned long long tb = __atomic_load_n(&acc[2], __ATOMIC_RELAXED);
+    if (tid == 0) {
+      unsigned long long *old = c->acc[(level + 2) % 3];
+      old[0] = old[1] = old[2] = 0;
+      *hcnt = 0;
+      c->levels = (int32_t)(level + 1);
+    }
+    if (tp == 0) {
+      dmax = (int)min(level + 1, (int64_t)255);
+      break;
+    }
+    alive = tb;
+    dir = (tf * 100ull > (unsigned long long)A.bu_percent * (unsigned long long)A.nnz) ? 1 : 0;
   }
   if (A.planes) {
     // the last level's distance bounds every distance; planes up to its top
     // bit were written
-    const int dmax = min(__atomic_load_n(&c->levels, __ATOMIC_RELAXED), 255);
     for (int64_t v = tid; v < A.n; v += nthreads) {
       if (dmax < 16)
         ms_write_rows<4>(A, v, dmax);
@@ -368,7 +354,7 @@ int ensure_ms_scratch(bfs_graph *g) {
   // frontier once, so a level has fewer than 2 nnz / kMsChunk chunks
   const int64_t hq_cap = 2 * (g->nnz / kMsChunk) + 64;
   void *p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  const size_t sizes[6] = {words * 8, words * 8, words * 8, kMsCtlBytes + kMsMaxBlocks * 3 * 8,
+  const size_t sizes[6] = {words * 8, words * 8, words * 8, kMsCtlBytes,
                            (size_t)hq_cap * 8, 8 * words * 8};
   for (int i = 0; i < 6; ++i) {
     if (hipMalloc(&p[i], sizes[i]) != hipSuccess) {
@@ -404,7 +390,6 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   A.hq_cap = g->ms.hq_cap;
   A.planes = k >= kMsPlaneMinK ? g->ms.planes : nullptr;
   A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
-  A.partials = g->ms.counters + kMsCtlBytes / 8;
   A.k = k;
   A.bu_percent = g->params.msbfs_bu_percent;
   A.heavy = kWave;
