@@ -248,8 +248,12 @@ int bfs_get_run_stats(bfs_graph_t g, bfs_run_stats *st, bfs_level_stats *levels,
  *   dist_out  device uint8[k][n], row-major: dist_out[i*n + v] = min(d, 255)
  *             where d is the distance from sources[i]; 255 also marks an
  *             unreached vertex.
+ * The first call on g allocates the batch scratch, which g keeps until
+ * bfs_destroy_graph (counted in device_bytes): 88 bytes per vertex (three
+ * 64-bit source sets and eight 64-bit distance bit planes), about nnz/64
+ * bytes of queue for long rows, and a 1 KiB control block.
  * Synchronous.  Errors: INVALID_ARG (k out of range, a source out of range,
- * null pointers), DEVICE.
+ * null pointers), OUT_OF_MEMORY (the scratch cannot be allocated), DEVICE.
  */
 int bfs_run_batch(bfs_graph_t g, const int32_t *sources, int32_t k, uint8_t *dist_out);
 
