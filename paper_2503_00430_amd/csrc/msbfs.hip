@@ -44,8 +44,9 @@ namespace {
 // so none is published here; the totals of level L are accumulated into
 // acc[L % 3] (one 128-byte line each), and level L's decide clears
 // acc[(L + 2) % 3], whose last readers passed a grid barrier before and whose
-// next writers come after another.  hcnt[L & 1] counts level L's chunk
-// entries and is cleared in the same way by level L's decide.
+// next writers come after another.  hcnt[L & 1] counts the chunk entries of
+// level L's frontier (queued before level L starts) and is cleared by level
+// L's decide.
 struct MsCtl {
   int32_t levels;  // levels run (for the caller; the kernel keeps its own count)
   int32_t pad;
@@ -106,13 +107,27 @@ __device__ void ms_write_rows(const MsArgs<RowT> &A, int64_t v, int dmax) {
 
 // Top-down rows longer than kMsChunk edges are not walked by the wavefront
 // that owns their vertex (a hub's row would take one dependent step per 64
-// edges): their kMsChunk-edge chunks are queued and, after a grid barrier,
-// spread over every wavefront.
+// edges): a vertex with such a row queues its kMsChunk-edge chunks when it
+// enters the frontier (at the start, or in the finalize pass of the level
+// that finds it), and in a top-down level every wavefront takes chunks from
+// the queue once its own words are done.  In the finalize pass a workgroup
+// collects its long rows in LDS and reserves their queue entries with one
+// atomic, so the queue counter sees one request per workgroup rather than
+// one per hub.
 constexpr int64_t kMsChunk = 1024;
+constexpr int kMsHubList = 256;  // long rows a workgroup collects per level (more go straight to the queue)
+
+template <class RowT>
+__device__ void ms_queue_chunks(const MsArgs<RowT> &A, int64_t v, int64_t deg, unsigned long long *hcnt) {
+  const uint64_t nch = (uint64_t)((deg + kMsChunk - 1) / kMsChunk);
+  const unsigned long long base = atomicAdd(hcnt, (unsigned long long)nch);
+  for (uint64_t k = 0; k < nch; ++k)
+    if ((int64_t)(base + k) < A.hq_cap) A.hq[base + k] = (k << 32) | (uint32_t)v;
+}
 
 // Top-down expansion of the wavefront's 64 vertices starting at v0.
 template <class RowT>
-__device__ void ms_td(const MsArgs<RowT> &A, int64_t v0, unsigned long long *hcnt) {
+__device__ void ms_td(const MsArgs<RowT> &A, int64_t v0) {
   const int lane = lane_id();
   const int64_t v = v0 + lane;
   const uint64_t f = v < A.n ? A.front[v] : 0ull;
@@ -121,13 +136,7 @@ __device__ void ms_td(const MsArgs<RowT> &A, int64_t v0, unsigned long long *hcn
     beg = (int64_t)A.rp[v];
     end = (int64_t)A.rp[v + 1];
   }
-  if (f && end - beg > kMsChunk) {  // a long row: queue its chunks for every wavefront
-    const uint64_t nch = (uint64_t)((end - beg + kMsChunk - 1) / kMsChunk);
-    const unsigned long long base = atomicAdd(hcnt, (unsigned long long)nch);
-    for (uint64_t k = 0; k < nch; ++k)
-      if ((int64_t)(base + k) < A.hq_cap) A.hq[base + k] = (k << 32) | (uint32_t)v;
-    beg = end = 0;
-  }
+  if (end - beg > kMsChunk) beg = end = 0;  // a long row: its chunks are queued
   const bool heavy = (end - beg) > A.heavy;
   if (f && !heavy) {
     for (int64_t j = beg; j < end; ++j) {
@@ -198,6 +207,10 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   const int64_t nwords = (A.n + kWave - 1) / kWave;
   MsCtl *c = A.ctl;
   __shared__ unsigned long long part[3][16];
+  __shared__ uint32_t hub_v[kMsHubList], hub_off[kMsHubList];
+  __shared__ uint32_t hub_n, hub_chunks;
+  __shared__ unsigned long long hub_base;
+  if (threadIdx.x == 0) hub_n = hub_chunks = 0;
 
   // Initialisation: empty sets, every distance 255 (unreached).
   for (int64_t v = tid; v < A.n; v += nthreads) {
@@ -224,7 +237,9 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     const int32_t s = c->src[tid];
     const unsigned long long bit = 1ull << tid;
     atomicOr(reinterpret_cast<unsigned long long *>(A.seen + s), bit);
-    atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
+    const uint64_t was = atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
+    const int64_t deg = (int64_t)A.rp[s + 1] - (int64_t)A.rp[s];
+    if (was == 0 && deg > kMsChunk) ms_queue_chunks(A, s, deg, &c->hcnt[0]);
     if (!A.planes) A.dist8[(int64_t)tid * A.n + s] = 0;
   }
   grid.sync();
@@ -236,12 +251,11 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
     unsigned long long *hcnt = &c->hcnt[level & 1];
     for (int64_t w = wave; w < nwords; w += nwaves) {
       if (dir == 0)
-        ms_td(A, w * kWave, hcnt);
+        ms_td(A, w * kWave);
       else
         ms_bu(A, w * kWave, alive);
     }
     if (dir == 0) {  // the long rows' chunks, one per wavefront
-      grid.sync();
       const int64_t nh = min((int64_t)__atomic_load_n(hcnt, __ATOMIC_RELAXED), A.hq_cap);
       for (int64_t i = wave; i < nh; i += nwaves) {
         const uint64_t e = A.hq[i];
@@ -273,8 +287,18 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
         if (nb) {
           A.seen[v] = s | nb;
           pairs += (unsigned long long)__popcll(nb);
-          fedges += (unsigned long long)((int64_t)A.rp[v + 1] - (int64_t)A.rp[v]);
+          const int64_t deg = (int64_t)A.rp[v + 1] - (int64_t)A.rp[v];
+          fedges += (unsigned long long)deg;
           bits |= nb;
+          if (deg > kMsChunk) {  // a long row enters the frontier: collect it
+            const uint32_t slot = atomicAdd(&hub_n, 1u);
+            if (slot < (uint32_t)kMsHubList) {
+              hub_v[slot] = (uint32_t)v;
+              hub_off[slot] = atomicAdd(&hub_chunks, (uint32_t)((deg + kMsChunk - 1) / kMsChunk));
+            } else {
+              ms_queue_chunks(A, v, deg, &c->hcnt[(level + 1) & 1]);
+            }
+          }
         }
         if (A.planes) {
           for (int b = 0; b < 8; ++b) {
@@ -294,6 +318,22 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
         any &= any - 1;
         if ((nb >> i) & 1ull) __builtin_nontemporal_store(dval, A.dist8 + (int64_t)i * A.n + v);
       }
+    }
+    __syncthreads();
+    if (hub_n) {  // reserve the collected rows' chunks with one atomic, then write them
+      if (threadIdx.x == 0) hub_base = atomicAdd(&c->hcnt[(level + 1) & 1], (unsigned long long)hub_chunks);
+      __syncthreads();
+      const uint32_t nl = min(hub_n, (uint32_t)kMsHubList);
+      for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+        const int64_t v = hub_v[i];
+        const int64_t deg = (int64_t)A.rp[v + 1] - (int64_t)A.rp[v];
+        const uint64_t nch = (uint64_t)((deg + kMsChunk - 1) / kMsChunk);
+        const unsigned long long at = hub_base + hub_off[i];
+        for (uint64_t k = 0; k < nch; ++k)
+          if ((int64_t)(at + k) < A.hq_cap) A.hq[at + k] = (k << 32) | (uint32_t)v;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) hub_n = hub_chunks = 0;
     }
     pairs = wave_sum(pairs);
     fedges = wave_sum(fedges);
