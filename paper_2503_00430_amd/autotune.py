@@ -83,6 +83,38 @@ def _time_batch(g, sources, out8, ref):
     return -t  # larger is better
 
 
+def descend(space: dict, start: dict, score, apply, passes: int = 2, log=print, name: str = "") -> tuple:
+    """Coordinate descent over `space` (parameter -> candidate values) from
+    `start`.  `apply(params)` installs a full parameter set and returns False
+    when the library rejects it; `score()` measures the installed set
+    (larger is better).  A candidate replaces the best only when it scores
+    more than 1 % higher; a pass that changes nothing ends the search.
+    Leaves the best set installed and returns (best, best_score)."""
+    best = dict(start)
+    if not apply(best):
+        raise ValueError("the starting parameters are rejected")
+    best_score = score()
+    log(f"[autotune] {name}: start {best_score:.4g}")
+    for _ in range(passes):
+        improved = False
+        for key, values in space.items():
+            for v in values:
+                if v == best[key]:
+                    continue
+                trial = dict(best, **{key: v})
+                if not apply(trial):
+                    continue  # an invalid combination (e.g. t1 >= t2)
+                sc = score()
+                if sc > best_score * 1.01:
+                    best, best_score, improved = trial, sc, True
+                    log(f"[autotune] {key}={v}: {sc:.4g}")
+            apply(best)
+        if not improved:
+            break
+    apply(best)
+    return best, best_score
+
+
 def tune(g, sources, mode: str = "single", passes: int = 2, log=print) -> dict:
     """Coordinate descent; returns the best parameter dict (full bfs_params)."""
     import torch
@@ -108,29 +140,14 @@ def tune(g, sources, mode: str = "single", passes: int = 2, log=print) -> dict:
         def score():
             _time_single(g, sources[:2], dist, None)  # warm
             return max(_time_single(g, sources, dist, ref) for _ in range(2))
-    best = dict(base)
-    L.bfs_set_params(g, **best)
-    best_score = score()
-    log(f"[autotune] {mode}: start {best_score:.4g}")
-    for _ in range(passes):
-        improved = False
-        for name, values in space.items():
-            for v in values:
-                if v == best[name]:
-                    continue
-                trial = dict(best, **{name: v})
-                try:
-                    L.bfs_set_params(g, **trial)
-                except L.BfsError:
-                    continue  # an invalid combination (e.g. t1 >= t2)
-                sc = score()
-                if sc > best_score * 1.01:
-                    best, best_score, improved = trial, sc, True
-                    log(f"[autotune] {name}={v}: {sc:.4g}")
-            L.bfs_set_params(g, **best)
-        if not improved:
-            break
-    L.bfs_set_params(g, **best)
+    def apply(p):
+        try:
+            L.bfs_set_params(g, **p)
+        except L.BfsError:
+            return False
+        return True
+
+    best, _ = descend(space, base, score, apply, passes, log, mode)
     return best
 
 
