@@ -408,7 +408,7 @@ def main():
                     help="only run the batched section (RMAT-22, 64 sources), e.g. to profile its kernel")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the search runs on a single device).", file=sys.stderr)
         sys.exit(2)
 
