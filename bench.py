@@ -58,6 +58,15 @@ def make_graph(name):
     return g, graphgen.sources(g, nsrc), rp32
 
 
+def make_handle(bfs, g, rp32=False):
+    """The graph as every timed section creates it: hub-first rows
+    (BFS_SORT_NEIGHBORS) and the autotuned parameters of its graph class.
+    Returns (handle, tuned parameters applied or None)."""
+    from paper_2503_00430_amd import autotune as at
+    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS | (bfs.BFS_ROWPTR32 if rp32 else 0))
+    return gh, at.apply_tuned(gh)
+
+
 def bu_launch_bytes(lv, n, row_ptr_bytes, with_parent=True):
     """Algorithmic bytes of one bottom-up level: visited words read, row
     bounds of the scanned vertices, neighbour ids up to the first hit,
@@ -88,23 +97,69 @@ def measured_traffic(workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(g, sources, budget_s=20.0, max_sources=8):
-    """The oracle (serial C BFS, one thread) on a bounded sample of sources."""
+def host_info():
+    """CPU model and core counts of the machine the CPU figures ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(g, sources, budget_s=20.0):
+    """The oracle (serial C BFS with parents, one thread pinned to one core)
+    on the workload's sources in order, until `budget_s` of CPU time is
+    spent (every source when they fit): harmonic-mean GTEPS, m_s / t_s per
+    source with t_s the oracle's own clock around initialisation plus
+    traversal."""
     import oracle
-    teps, used = [], []
-    t_total = 0.0
-    for s in sources[:max_sources]:
-        d, _, secs = oracle.bfs_timed(g, int(s), want_parent=True)
-        st = oracle.level_stats(g, d)
-        teps.append(st["m_s"] / secs)
-        used.append(int(s))
-        t_total += secs
-        if t_total > budget_s:
-            break
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})  # this thread only; restored below
+    try:
+        teps, t_total = [], 0.0
+        for s in sources:
+            d, _, secs = oracle.bfs_timed(g, int(s), want_parent=True)
+            teps.append(oracle.level_stats(g, d)["m_s"] / secs)
+            t_total += secs
+            if t_total > budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     hm = len(teps) / sum(1.0 / t for t in teps)
-    return {"value": hm / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{len(used)} of the {len(sources)} sources on the full graph, "
-                      f"serial FIFO BFS with parents, {t_total:.1f} s of CPU time"}
+    return {"value": round(hm / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(teps)} of the {len(sources)} sources in order on the full graph "
+                      f"(budget {budget_s:.0f} s of CPU time, {t_total:.1f} s used), serial FIFO "
+                      f"BFS with parents, pinned to core {core}",
+            "min_gteps": round(min(teps) / 1e9, 5), "max_gteps": round(max(teps) / 1e9, 5),
+            "host": host_info()}
+
+
+def golden_runs(name):
+    """The oracle's per-source digests of a workload (tests/golden/digests.json,
+    written from the oracle by tests/golden/make_digests.py), or None."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "digests.json")) as f:
+            return json.load(f)[name]["runs"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def parity(name, outputs, key="dist_sha256"):
+    """Compares the SHA-256 of each output with the oracle's digest of the
+    same source: "k/K" sources bit-identical (outputs: {source: array})."""
+    runs = golden_runs(name)
+    if runs is None:
+        return "no digests"
+    want = {r["source"]: r[key] for r in runs}
+    ok = sum(1 for s, a in outputs.items()
+             if want.get(int(s)) == hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest())
+    return f"{ok}/{len(outputs)}"
 
 
 def cpu_openmp(g, sources, budget_s=8.0, max_sources=4):
@@ -132,22 +187,25 @@ def cpu_openmp(g, sources, budget_s=8.0, max_sources=4):
     return out
 
 
-def bench_batched(bfs, torch, reps=3):
-    """RMAT scale 22, 64 sources: one bfs_run_batch against 64 bfs_run calls."""
+def bench_batched(bfs, torch, reps=3, cpu=True):
+    """RMAT scale 22, 64 sources: one bfs_run_batch against 64 bfs_run calls;
+    every batch row and every plain result hashed against the oracle's
+    digests (outside the timed calls)."""
     g, sources, _ = make_graph("rmat22")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS)
-    autotune.apply_tuned(gh)
+    gh, _ = make_handle(bfs, g)
     out8 = torch.empty((len(sources), g.n), dtype=torch.uint8, device="cuda")
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     bfs.bfs_run_batch(gh, sources, out8)  # warm-up
-    edges, plain = {}, []
-    for _ in range(reps):
+    edges, plain, plain_out = {}, [], {}
+    for rep in range(reps):
         tot = 0.0
         for s in sources:
             bfs.bfs_run(gh, int(s), dist)
             run, _ = bfs.bfs_get_run_stats(gh)
             edges[int(s)] = run["edges"]
-            tot += run["host_ms"]
+            tot += run["host_ms"]  # the call's own wall time
+            if rep == reps - 1:
+                plain_out[int(s)] = dist.cpu().numpy().astype("<i4")
         plain.append(tot)
     batch = []
     for _ in range(reps):
@@ -155,15 +213,53 @@ def bench_batched(bfs, torch, reps=3):
         t0 = time.perf_counter()
         bfs.bfs_run_batch(gh, sources, out8)
         batch.append((time.perf_counter() - t0) * 1e3)
+    rows = out8.cpu().numpy()
     m = sum(edges.values())
     tb, tp = statistics.median(batch), statistics.median(plain)
     del out8
     visited = ablation(bfs, torch, gh, sources[:4])
     gh.close()
-    return {"workload": "rmat22_ef16_64src", "n": g.n, "nnz": g.nnz, "batch_ms": round(tb, 3),
-            "plain_64_ms": round(tp, 3), "batch_gteps": round(m / tb / 1e6, 3),
-            "plain_gteps": round(m / tp / 1e6, 3), "speedup": round(tp / tb, 3),
-            "visited_test_ablation_4src_td_only": visited}
+    out = {"workload": "rmat22_ef16_64src", "n": g.n, "nnz": g.nnz, "batch_ms": round(tb, 3),
+           "plain_64_ms": round(tp, 3), "batch_gteps": round(m / tb / 1e6, 3),
+           "plain_gteps": round(m / tp / 1e6, 3), "speedup": round(tp / tb, 3),
+           "parity_batch_rows": parity("rmat22", {int(s): rows[i] for i, s in enumerate(sources)},
+                                       "dist8_sha256"),
+           "parity_plain": parity("rmat22", plain_out),
+           "visited_test_ablation_4src_td_only": visited}
+    if cpu:
+        out["cpu_oracle"] = cpu_baseline(g, sources, budget_s=10.0)
+    return out
+
+
+def bench_small(bfs, torch, reps=20, cpu=True):
+    """RMAT scale 16 (int32 row offsets), 16 sources: latency of one search
+    (launch-bound, cache-resident), median over `reps` runs per source."""
+    g, sources, rp32 = make_graph("rmat16")
+    gh, _ = make_handle(bfs, g, rp32)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    per, outs = {}, {}
+    for s in sources:
+        bfs.bfs_run(gh, int(s), dist, parent)  # warm-up
+        for _ in range(reps):
+            bfs.bfs_run(gh, int(s), dist, parent)
+            run, _ = bfs.bfs_get_run_stats(gh)
+            per.setdefault(int(s), [run["edges"], [], []])
+            per[int(s)][1].append(run["host_ms"])
+            per[int(s)][2].append(run["device_ms"])
+        outs[int(s)] = dist.cpu().numpy().astype("<i4")
+    gh.close()
+    host_us = [statistics.median(t) * 1e3 for _, t, _ in per.values()]
+    dev_us = [statistics.median(t) * 1e3 for _, _, t in per.values()]
+    teps = [e / (statistics.median(t) / 1e3) for e, t, _ in per.values()]
+    out = {"workload": "rmat16_ef16_16src_int32_rowptr", "n": g.n, "nnz": g.nnz,
+           "us_per_bfs_median": round(statistics.median(host_us), 2),
+           "us_per_bfs_device_median": round(statistics.median(dev_us), 2),
+           "gteps_hm": round(len(teps) / sum(1.0 / t for t in teps) / 1e9, 3),
+           "parity": parity("rmat16", outs)}
+    if cpu:
+        out["cpu_oracle"] = cpu_baseline(g, sources, budget_s=5.0)
+    return out
 
 
 POLICY_NAMES = {1: "alpha_beta (BFS-Hybrid dagger)", 2: "frontier_5pct (BFS-Hybrid)", 3: "td_only"}
@@ -249,31 +345,36 @@ def ablation(bfs, torch, gh, sources, reps=1):
     return out
 
 
-def bench_mesh(bfs, torch, reps=2):
+def bench_mesh(bfs, torch, reps=2, cpu=True):
     """4096 x 4096 perturbed lattice, 16 sources (top-down only, captured loop)."""
     g, sources, _ = make_graph("grid4096")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS)
-    autotune.apply_tuned(gh)
+    gh, _ = make_handle(bfs, g)
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     bfs.bfs_run(gh, int(sources[0]), dist)  # warm-up (captures the level loop)
-    per = {}
+    per, outs = {}, {}
     levels = []
-    for _ in range(reps):
+    for rep in range(reps):
         for s in sources:
             bfs.bfs_run(gh, int(s), dist)
             run, _ = bfs.bfs_get_run_stats(gh)
             per.setdefault(int(s), [run["edges"], []])[1].append(run["host_ms"] / 1e3)
             levels.append(run["levels"])
+            if rep == reps - 1:
+                outs[int(s)] = dist.cpu().numpy().astype("<i4")
     teps = [e / statistics.median(t) for e, t in per.values()]
     policies = policy_study(bfs, torch, gh, sources[:4], reps=1)
     visited = ablation(bfs, torch, gh, sources[:4])
     gh.close()
     hm = len(teps) / sum(1.0 / t for t in teps) / 1e9
     mean_ms = statistics.mean(statistics.median(t) for _, t in per.values()) * 1e3
-    return {"workload": "grid4096_p0.1_16src", "n": g.n, "nnz": g.nnz, "gteps_hm": round(hm, 4),
-            "ms_per_bfs": round(mean_ms, 3), "levels_mean": round(statistics.mean(levels), 1),
-            "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2),
-            "policy_study_4src": policies, "visited_test_ablation_4src": visited}
+    out = {"workload": "grid4096_p0.1_16src", "n": g.n, "nnz": g.nnz, "gteps_hm": round(hm, 4),
+           "ms_per_bfs": round(mean_ms, 3), "levels_mean": round(statistics.mean(levels), 1),
+           "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2),
+           "parity": parity("grid4096", outs),
+           "policy_study_4src": policies, "visited_test_ablation_4src": visited}
+    if cpu:
+        out["cpu_oracle"] = cpu_baseline(g, sources, budget_s=10.0)
+    return out
 
 
 # Serving pool: RMAT scales 14-22 and 23, perturbed lattices without
@@ -310,8 +411,7 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
     for kind, size in SERVE_POOL:
         g = _serve_graph(kind, size)
         graphs.append(g)
-        handles.append(bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS))
-        autotune.apply_tuned(handles[-1])
+        handles.append(make_handle(bfs, g)[0])
         edges.append(_component_edges(g))
         nz.append(np.flatnonzero(g.degree > 0))
     rng = np.random.default_rng(seed)
@@ -393,6 +493,25 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
     return out
 
 
+def copy_bandwidth(torch, reps=10):
+    """A plain 1 GiB device-to-device copy timed with events on the current
+    stream: (bytes read + bytes written) / time, in GB/s (the streaming
+    ceiling this GPU reaches, beside the published 8 TB/s)."""
+    x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return round(2 * (1 << 30) / secs / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,22 +551,23 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.batched_only:
-        print(json.dumps({"batched": bench_batched(bfs, torch)}), flush=True)
+        print(json.dumps({"batched": bench_batched(bfs, torch, cpu=False)}), flush=True)
         return
 
     t0 = time.time()
     g, sources, rp32 = make_graph(args.workload)
     log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f} s")
-    gh = bfs.bfs_create_graph(g.row_ptr, g.col_idx, CREATE_FLAGS | (bfs.BFS_ROWPTR32 if rp32 else 0))
+    gh, tuned = make_handle(bfs, g, rp32)
     info = bfs.bfs_graph_info_get(gh)
-    tuned = autotune.apply_tuned(gh)
     params = bfs.bfs_get_params(gh)
-    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    # one output pair per source (HBM has room: 2 x 64 x 4N bytes at scale
+    # 24), so every timed search's own result can be hashed afterwards
+    dists = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in sources]
+    parents = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in sources]
 
     def step(record):
-        for s in sources:
-            bfs.bfs_run(gh, int(s), dist, parent)
+        for i, s in enumerate(sources):
+            bfs.bfs_run(gh, int(s), dists[i], parents[i])
             if record is not None:
                 run, levels = bfs.bfs_get_run_stats(gh)
                 record.append((int(s), run, levels))
@@ -464,6 +584,10 @@ def main():
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     log(f"timed {args.steps} steps in {t_end - t_start:.3f} s")
+    # the distances of the last timed step, against the oracle's digests
+    timed_parity = parity(args.workload, {int(s): dists[i].cpu().numpy().astype("<i4")
+                                          for i, s in enumerate(sources)})
+    log(f"parity of the timed results: {timed_parity}")
 
     # per-source median wall time -> TEPS; harmonic mean over sources
     def hm_gteps(recs, key):
@@ -543,6 +667,9 @@ def main():
                    "params": {k: v for k, v in bfs.bfs_get_params(gh).items()
                               if k not in ("collect_timing",)},
                    "tuned_params_applied": bool(tuned), "parents": True},
+        "parity": {"dist_bit_exact_vs_oracle": timed_parity,
+                   "how": "SHA-256 of each timed search's distances against the oracle's digest "
+                          "of the same source (tests/golden/digests.json)"},
         "roofline": roofline,
         "gteps_device_time_hm": round(gteps_dev_hm, 3),
         "gteps_host_loop_hm": round(gteps_host_loop, 3),
@@ -552,19 +679,24 @@ def main():
         "policy_study_16src": policies,
     }
     gh.close()
-    del dist, parent
+    del dists, parents
     torch.cuda.empty_cache()
+    if roofline is not None:
+        roofline["measured_copy_GBps"] = copy_bandwidth(torch)
+    cpu = not args.no_cpu_baseline
     if not args.no_extras:
+        log("small section (rmat16 latency)")
+        out["small"] = bench_small(bfs, torch, cpu=cpu)
         log("batched section (rmat22)")
-        out["batched"] = bench_batched(bfs, torch)
+        out["batched"] = bench_batched(bfs, torch, cpu=cpu)
         torch.cuda.empty_cache()
         log("mesh section (grid4096)")
-        out["mesh"] = bench_mesh(bfs, torch)
+        out["mesh"] = bench_mesh(bfs, torch, cpu=cpu)
         torch.cuda.empty_cache()
         log("serving section (12-graph pool)")
         out["serving"] = bench_serving(bfs, torch)
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
+    if cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, sources)
         log("cpu context (OpenMP kernels of the paper)")

@@ -18,6 +18,9 @@ Contents
   algo_bytes               the byte model of each level.
   msbfs_dist8              batched distances saturated to uint8.
   validate                 independent invariant checker (validate.py).
+  check_tree               the parent invariants of validate in one C pass
+                           (for full-size trees whose distances are already
+                           known to be exact).
 
 All arithmetic here is exact integer arithmetic.
 """
@@ -71,6 +74,8 @@ def _bind(lib):
     lib.oracle_bfs.restype = i64
     lib.oracle_bottom_up_profile.argtypes = [i64, vp, vp, vp, i32, vp]
     lib.oracle_bottom_up_profile.restype = None
+    lib.oracle_check_tree.argtypes = [i64, vp, vp, i32, vp, vp, vp]
+    lib.oracle_check_tree.restype = None
     return lib
 
 
@@ -190,6 +195,26 @@ def bottom_up_profile(g, dist: np.ndarray, level: int, lib=None) -> dict:
                                  int(level), out.ctypes.data)
     return {"unvisited": int(out[0]), "examined": int(out[1]), "found": int(out[2]),
             "full": int(out[3])}
+
+
+def check_tree(g, source: int, dist: np.ndarray, parent: np.ndarray, lib=None) -> list[str]:
+    """Parent invariants P1-P3 of validate.py (see there) checked in C, one
+    pass over the rows; meant for distance arrays already shown exact.
+    Returns the violated invariants (empty when the tree is valid)."""
+    lib = lib or load()
+    rp, col = _csr_arrays(g)
+    n = len(rp) - 1
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    p = np.ascontiguousarray(parent, dtype=np.int32)
+    if d.shape != (n,) or p.shape != (n,):
+        return [f"dist/parent shapes {d.shape}/{p.shape}, expected ({n},)"]
+    out = np.zeros(5, np.int64)
+    lib.oracle_check_tree(n, rp.ctypes.data, col.ctypes.data, int(source), d.ctypes.data,
+                          p.ctypes.data, out.ctypes.data)
+    names = ["P1: parent[source] != source", "P3: parent set exactly where dist is not -1",
+             "P2: parent one level up", "P2: parent is a neighbour"]
+    return [f"{names[k]}: {int(out[k])} vertices violate it (first v={int(out[4])})"
+            for k in range(4) if out[k]]
 
 
 def bitmap_bytes(n: int) -> int:

@@ -139,3 +139,42 @@ void oracle_bottom_up_profile(int64_t n, const int64_t *row_ptr, const int32_t *
   out[2] = found;
   out[3] = full;
 }
+
+/*
+ * Check of a BFS tree (the parent convention above) against a distance
+ * array that is already known to be exact.  For every vertex v it tests
+ *   out[0]  P1: parent[source] == source;
+ *   out[1]  P3: parent[v] == -1 exactly when dist[v] == -1;
+ *   out[2]  P2: for reached v != source, parent[v] is a vertex id whose
+ *               distance is dist[v] - 1;
+ *   out[3]  P2: for reached v != source, parent[v] occurs in row v (the pair
+ *               is an edge).
+ * Each out[k] counts the vertices that violate it; out[4] is the first such
+ * vertex (or -1).  One pass over the rows of the reached vertices.
+ */
+void oracle_check_tree(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t source,
+                       const int32_t *dist, const int32_t *parent, int64_t *out) {
+  int64_t bad[4] = {0, 0, 0, 0};
+  int64_t first = -1;
+  for (int64_t v = 0; v < n; ++v) {
+    int viol = 0;
+    const int32_t p = parent[v];
+    if (v == source) {
+      if (p != source) { ++bad[0]; viol = 1; }
+    } else if (dist[v] < 0) {
+      if (p != -1) { ++bad[1]; viol = 1; }
+    } else if (p == -1) {
+      ++bad[1]; viol = 1;
+    } else if (p < -1 || p >= n || dist[p] != dist[v] - 1) {
+      ++bad[2]; viol = 1;
+    } else {
+      int edge = 0;
+      for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j)
+        if (col[j] == p) { edge = 1; break; }
+      if (!edge) { ++bad[3]; viol = 1; }
+    }
+    if (viol && first < 0) first = v;
+  }
+  for (int k = 0; k < 4; ++k) out[k] = bad[k];
+  out[4] = first;
+}

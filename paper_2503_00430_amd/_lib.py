@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 import threading
 
 import numpy as np
@@ -161,6 +162,11 @@ class Graph:
             self.handle = None
 
     def __del__(self):
+        # During interpreter shutdown the HIP runtime (and torch's use of it)
+        # may already be torn down: a graph still open then is left to the
+        # process exit instead of issuing frees, graph and stream destroys.
+        if sys.is_finalizing():
+            return
         try:
             if self.handle and _lib is not None:
                 _lib.bfs_destroy_graph(self.handle)
@@ -276,6 +282,17 @@ def bfs_run_batch(g: Graph, sources, dist8):
 class Server:
     def __init__(self, handle):
         self.handle = handle
+
+    def __del__(self):
+        # as Graph.__del__: nothing is issued once the interpreter is shutting down
+        if sys.is_finalizing():
+            return
+        try:
+            if self.handle and _lib is not None:
+                _lib.bfs_serve_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
 
     def close(self):
         if self.handle:

@@ -77,6 +77,12 @@ __device__ __forceinline__ void block_partials(const DevG<RowT> &G, const unsign
   }
 }
 
+// Marks the running level as having lost queue entries (an append past a
+// queue's end).  Any thread; the decide step reads the flag.
+__device__ __forceinline__ void flag_overflow(Ctl *c) {
+  __hip_atomic_fetch_or(&c->overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Claims vertex v: true for exactly one caller per search.
 __device__ __forceinline__ bool claim(uint64_t *vis, int32_t v) {
   const uint64_t bit = 1ull << (v & 63);
@@ -157,9 +163,11 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       const unsigned slot = base + lanes_below(m);
       if (slot < cap)
         (bb == kSmall ? S.small : S.medium)[slot] = v;
-      else if (gbase + (slot - first_over) < G.qcap) {  // past the end: dropped, the decide step stops
+      else if (gbase + (slot - first_over) < G.qcap && gbase + (slot - first_over) >= gbase) {
         global_queue(G, qn, bb)[gbase + (slot - first_over)] = v;
         if (G.slot) G.slot[v] = (int32_t)(gbase + (slot - first_over));
+      } else {
+        flag_overflow(G.ctl);  // past the end: dropped, and the decide step stops the search
       }
     }
   }
@@ -176,8 +184,10 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       const uint64_t e = ((uint64_t)k << 32) | (uint32_t)v;
       if (slot < cap)
         S.large[slot] = e;
-      else if (gbase + (slot - first_over) < G.lcap)
+      else if (gbase + (slot - first_over) < G.lcap && gbase + (slot - first_over) >= gbase)
         gq[gbase + (slot - first_over)] = e;
+      else
+        flag_overflow(G.ctl);
     }
   }
 }
@@ -203,6 +213,10 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
     const unsigned n = S.cnt[b] < cap ? S.cnt[b] : cap;
     count[b] = n;
     gbase[b] = n ? atomicAdd(&G.ctl->qcnt[qn][b], n) : 0;
+    // a range past the queue's end (or past 2^32 appends) loses entries: the
+    // search stops at this level's decide step
+    const uint64_t qend = (uint64_t)gbase[b] + n;
+    if (n && qend > (b == kLarge ? G.lcap : G.qcap)) flag_overflow(G.ctl);
   }
   __syncthreads();
   int32_t *qs = global_queue(G, qn, kSmall);
@@ -318,6 +332,17 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
   }
 }
 
+// Moves the control block's level number on with an agent-scope atomic
+// exchange and waits for it to return, i.e. until it has been performed at
+// the device-wide coherence point.  A plain store would sit in this XCD's L2
+// (written back only at a release or at the kernel's end), where a workgroup
+// on another XCD, which reads the number with an agent-scope load, need not
+// see it.  One thread.
+__device__ __forceinline__ void publish_level(Ctl *c, int32_t level) {
+  (void)__hip_atomic_exchange(&c->level, level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // Level bookkeeping and the direction rule, applied by one thread to the
 // level's totals {found, degree sum of found, scanned, examined}.
 // `bumped` >= 0: the caller has already stored level bumped + 1 and waited
@@ -326,13 +351,11 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
                              int32_t bumped = -1) {
   const int32_t L = bumped >= 0 ? bumped : c->level;
   const int32_t cur = c->dir;
-  // The level number changes first, and reaches the cache before any other
-  // field changes: a workgroup of this level's launch that starts only now
-  // reads the fields, then the number, and leaves when the number moved on.
-  if (bumped < 0) {
-    c->level = L + 1;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
+  // The level number changes first, and has been performed at device scope
+  // before any other field changes: a workgroup of this level's launch that
+  // starts only now reads the fields, then the number, and leaves when the
+  // number moved on (see publish_level).
+  if (bumped < 0) publish_level(c, L + 1);
   const int64_t found = (int64_t)tot[0];
   const int64_t fdeg = (int64_t)tot[1];
   if (L < c->rec_cap) {
@@ -359,7 +382,8 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     // appended once per racing discoverer; a set that outgrew its queues
     // lost entries, so the search ends here and the host reports it
     const unsigned *q = c->qcnt[c->qcur];
-    if (q[kSmall] > c->qcap[0] || q[kMedium] > c->qcap[0] || q[kLarge] > c->qcap[1]) {
+    if (__hip_atomic_load(&c->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+        q[kSmall] > c->qcap[0] || q[kMedium] > c->qcap[0] || q[kLarge] > c->qcap[1]) {
       c->overflow = 1;
       c->done = 1;
       c->conv = kConvNone;
@@ -834,7 +858,7 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
     const int w = threadIdx.x >> 6;
     if (threadIdx.x == 0) {  // first (see decide_apply), overlapping the reduction
       if (level < 0) level = G.ctl->level;
-      G.ctl->level = level + 1;
+      (void)__hip_atomic_exchange(&G.ctl->level, level + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -882,7 +906,8 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
   if (__shfl(arrived, 0) != ngroups - 1) return;
   if (lane == 0) {
     if (level < 0) level = G.ctl->level;
-    G.ctl->level = level + 1;  // first (see decide_apply); the exchange below waits for it
+    // first (see publish_level); the wait below covers it
+    (void)__hip_atomic_exchange(&G.ctl->level, level + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     atomicExch(&arrive[kArriveGroups * kLineU32], 0u);
   }
   // lane g * kPartials + k takes accumulator k of group g; sums over the

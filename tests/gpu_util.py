@@ -88,3 +88,58 @@ def check_single(g, gh, s, *, parent=True, ref=None, full_validate=True, check_l
                 assert lv["scanned"] == prof["unvisited"], (L, lv, prof)
                 assert lv["examined"] == prof["examined"], (L, lv, prof)
     return d, p, run, levels
+
+
+# ---------------------------------------------------------------------------
+# Full-size parity through the oracle's digests (tests/golden/digests.json,
+# written by tests/golden/make_digests.py from the oracle alone).
+
+_GOLDEN = None
+
+
+def golden():
+    global _GOLDEN
+    if _GOLDEN is None:
+        import json
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
+        with open(path) as f:
+            _GOLDEN = json.load(f)
+    return _GOLDEN
+
+
+def sha256(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def check_graph_digest(g, rec):
+    """The generated graph is the one the digests were taken on."""
+    import hashlib
+    assert (g.n, g.nnz) == (rec["n"], rec["nnz"]), (g.n, g.nnz, rec)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(g.row_ptr, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(g.col_idx, dtype="<i4").tobytes())
+    assert h.hexdigest() == rec["csr_sha256"], "generated graph differs from the one the digests were taken on"
+
+
+def check_run_against_digest(rec, dist, run, levels, params, n, nnz):
+    """One search against the oracle's record: dist bit-exact (SHA-256),
+    reached / edges / level count, per-level frontier sizes and degree sums,
+    and the direction schedule the oracle's replay of the run's rule gives."""
+    s = rec["source"]
+    assert sha256(dist.astype("<i4")) == rec["dist_sha256"], f"dist differs from the oracle's (source {s})"
+    assert run["reached"] == rec["reached"] and run["edges"] == rec["m_s"], (s, run, rec)
+    assert run["levels"] == rec["levels"], (s, run["levels"], rec["levels"])
+    h = np.array([lv["frontier"] for lv in levels], "<i8")
+    mf = np.array([lv["frontier_edges"] for lv in levels], "<i8")
+    if "h" in rec:
+        assert h.tolist() == rec["h"] and mf.tolist() == rec["mf"], s
+        stats = {"n": n, "nnz": nnz, "depth": rec["levels"], "h": np.array(rec["h"]),
+                 "mf": np.array(rec["mf"]), "mu": nnz - np.cumsum(rec["mf"])}
+        sched = oracle.replay_policy(stats, POLICY_NAMES[run["policy"]], params["alpha"], params["beta"])
+        assert [lv["direction"] for lv in levels] == sched, (s, sched)
+    else:
+        assert sha256(h) == rec["h_sha256"] and sha256(mf) == rec["mf_sha256"], s
+        if POLICY_NAMES[run["policy"]] == "td_only":
+            assert all(lv["direction"] == oracle.TD for lv in levels)

@@ -38,3 +38,32 @@ def test_bottom_up_byte_model_matches_oracle():
         counts = {"scanned": prof["unvisited"], "examined": prof["examined"],
                   "discovered": int(st["h"][L + 1]) if L + 1 < len(st["h"]) else 0}
         assert bench.bu_launch_bytes(counts, g.n, 8, with_parent=True) == model["levels"][L]
+
+
+def test_parity_report_counts_matching_digests():
+    """bench.parity counts outputs whose SHA-256 equals the oracle's digest:
+    the oracle's own distances give K/K, one changed value one less."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import graphgen
+    import oracle
+    g, srcs, _ = bench.make_graph("rmat16")
+    outs = {int(s): oracle.bfs(g, int(s), want_parent=False)[0].astype("<i4") for s in srcs}
+    assert bench.parity("rmat16", outs) == f"{len(srcs)}/{len(srcs)}"
+    s0 = int(srcs[0])
+    outs[s0] = outs[s0].copy()
+    outs[s0][np.flatnonzero(outs[s0] > 0)[0]] += 1
+    assert bench.parity("rmat16", outs) == f"{len(srcs) - 1}/{len(srcs)}"
+    assert graphgen is not None
+
+
+def test_cpu_baseline_pins_one_core_and_reports_host():
+    sys.path.insert(0, ROOT)
+    import bench
+    import graphgen
+    g = graphgen.rmat(10)
+    before = os.sched_getaffinity(0)
+    out = bench.cpu_baseline(g, graphgen.sources(g, 4), budget_s=1.0)
+    assert os.sched_getaffinity(0) == before
+    assert out["cores"] == 1 and out["kind"] == "oracle" and out["value"] > 0
+    assert "pinned to core" in out["sample"] and out["host"]["nproc"] >= 1

@@ -150,22 +150,29 @@ def test_bad_arguments(bfs, rmat16):
     gh.close()
 
 
-def test_rmat22_config(bfs):
-    """RMAT scale 22, 64 sources in one launch: 8 rows against the oracle in
-    full, every row's reached count against its source's component."""
-    from scipy.sparse import csr_matrix
-    from scipy.sparse.csgraph import connected_components
+@pytest.mark.parametrize("config", ["bench", "default"])
+def test_rmat22_config(bfs, config):
+    """RMAT scale 22, 64 sources in one launch, in the benchmark's
+    configuration (hub-first rows, tuned parameters) and with defaults: every
+    row equals the oracle's min(d, 255) (SHA-256 digests written from the
+    oracle), and so does every one of the 64 plain searches the benchmark
+    times beside the batch."""
+    import bench
+    from tests.gpu_util import check_graph_digest, golden, sha256
+    rec = golden()["rmat22"]
     say("generating rmat22")
-    g = graphgen.rmat(22)
-    gh = upload(g)
-    srcs = graphgen.sources(g, 64)
-    say("batch rmat22 k=64")
+    g, srcs, _ = bench.make_graph("rmat22")
+    check_graph_digest(g, rec["graph"])
+    assert [int(s) for s in srcs] == rec["sources"]
+    gh = bench.make_handle(bfs, g)[0] if config == "bench" else upload(g)
+    say("batch rmat22 k=64", config, bfs.bfs_get_params(gh))
     got = run_batch(bfs, gh, srcs)
-    pick = list(range(0, 64, 8))
-    np.testing.assert_array_equal(got[pick], expect(g, srcs[pick]))
-    a = csr_matrix((np.ones(g.nnz, np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
-    _, lab = connected_components(a, directed=False)
-    sizes = np.bincount(lab)
-    for i, s in enumerate(srcs):
-        assert int((got[i] != 255).sum()) == sizes[lab[s]]
+    for i, r in enumerate(rec["runs"]):
+        assert sha256(got[i]) == r["dist8_sha256"], f"row {i} (source {r['source']}) differs"
+    if config == "bench":
+        import torch
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for r in rec["runs"]:
+            bfs.bfs_run(gh, r["source"], dist)
+            assert sha256(dist.cpu().numpy().astype("<i4")) == r["dist_sha256"], r["source"]
     gh.close()

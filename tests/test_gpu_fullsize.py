@@ -1,45 +1,34 @@
-"""GPU parity at the full workload sizes, in the launch configuration the
-benchmark times (default tunables):
-  * RMAT scale 24, edge factor 16, int64 row offsets, 64 sources;
-  * 4096 x 4096 perturbed lattice (10 % deletion, 1 % shortcuts), 16 sources.
-A few sources are compared with the oracle in full (bit-exact distances,
-per-level schedule and work); every source is checked on a sample of
-vertices against local BFS properties and on its reached count against the
-connected component of its source."""
+"""GPU parity at the full workload sizes, every source compared bit for bit.
+
+The oracle's distances for every source of every full-size workload are
+stored as SHA-256 digests with their per-level statistics
+(tests/golden/digests.json, written by tests/golden/make_digests.py from the
+oracle alone).  Each GPU search here is hashed and compared with its digest;
+its per-level frontier sizes, degree sums and direction schedule must equal
+the oracle's replay, and its parent array must pass the tree check (every
+parent a neighbour one level up).
+
+Configurations:
+  * "bench": the graph exactly as bench.py creates it for its timed runs
+    (hub-first rows, the autotuned parameters of its graph class), with the
+    captured level loop the headline times and with the host-driven loop of
+    the instrumented pass;
+  * "default": flags 0 and default parameters.
+Workloads: RMAT scale 24 (int64 row offsets, 64 sources), the 4096 x 4096
+perturbed lattice (16 sources) and RMAT scale 16 (int32 row offsets, 16
+sources)."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
+import bench
 import graphgen
 import oracle
-from tests.gpu_util import check_single, gpu_bfs, library, say, upload
+from tests.gpu_util import (check_graph_digest, check_run_against_digest, golden, library, say,
+                            upload)
 
 pytestmark = pytest.mark.gpu
-
-
-def _component_sizes(g):
-    from scipy.sparse import csr_matrix
-    from scipy.sparse.csgraph import connected_components
-    a = csr_matrix((np.ones(g.nnz, np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
-    _, lab = connected_components(a, directed=False)
-    return lab, np.bincount(lab)
-
-
-def _sampled_checks(g, s, d, p, rng, k=20000):
-    """For sampled vertices v: neighbours within one level; a reached v != s
-    has a neighbour one level up and its parent is such a neighbour; an
-    unreached v has only unreached neighbours."""
-    assert d[s] == 0 and p[s] == s
-    vs = rng.integers(0, g.n, k)
-    rp, col = g.row_ptr, g.col_idx
-    for v in vs:
-        nb = col[rp[v]:rp[v + 1]]
-        dn = d[nb]
-        if d[v] < 0:
-            assert (dn < 0).all() and p[v] == -1
-        elif v != s:
-            assert (dn >= 0).all() and (np.abs(dn - d[v]) <= 1).all()
-            assert (dn == d[v] - 1).any()
-            assert p[v] in nb and d[p[v]] == d[v] - 1
 
 
 @pytest.fixture(scope="module")
@@ -47,52 +36,65 @@ def bfs():
     return library()
 
 
-@pytest.fixture(scope="module")
-def rmat24():
-    say("generating rmat24")
-    return graphgen.rmat(24)
+_GRAPHS = {}
 
 
-@pytest.fixture(scope="module")
-def grid4096():
-    say("generating grid4096")
-    return graphgen.grid(4096)
+def workload(name):
+    if name not in _GRAPHS:
+        _GRAPHS.clear()  # one full-size graph in host memory at a time
+        say("generating", name)
+        g, srcs, rp32 = bench.make_graph(name)
+        rec = golden()[name]
+        check_graph_digest(g, rec["graph"])
+        assert [int(s) for s in srcs] == rec["sources"]
+        _GRAPHS[name] = (g, srcs, rp32, rec)
+    return _GRAPHS[name]
 
 
-def test_rmat24(bfs, rmat24):
-    g = rmat24
-    gh = upload(g)  # int64 row offsets
-    info = bfs.bfs_graph_info_get(gh)
-    assert info["row_ptr_bytes"] == 8 and info["nnz"] == g.nnz
-    srcs = graphgen.sources(g, 64)
-    lab, sizes = _component_sizes(g)
-    for i, s in enumerate(srcs[:2]):
-        say("rmat24 full parity source", s)
-        check_single(g, gh, s, full_validate=(i == 0))
-    rng = np.random.default_rng(0)
-    for s in srcs:
-        say("rmat24 sampled source", s)
-        d, p = gpu_bfs(gh, s)
+def run_all(bfs, g, gh, rec, parents, pool):
+    """Every source of the record: digest, statistics, schedule; parent
+    trees checked on the host in `pool` while the GPU runs the next ones."""
+    import torch
+    params = bfs.bfs_get_params(gh)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    par = torch.empty(g.n, dtype=torch.int32, device="cuda") if parents else None
+    checks = []
+    for r in rec["runs"]:
+        s = r["source"]
+        bfs.bfs_run(gh, s, dist, par)
         run, levels = bfs.bfs_get_run_stats(gh)
-        assert run["reached"] == sizes[lab[s]] == int((d >= 0).sum())
-        _sampled_checks(g, s, d, p, rng, k=2000)
-    gh.close()
+        d = dist.cpu().numpy()
+        check_run_against_digest(r, d, run, levels, params, g.n, g.nnz)
+        if parents:
+            p = par.cpu().numpy()
+            checks.append((s, pool.submit(oracle.check_tree, g, s, d, p)))
+    for s, f in checks:
+        assert f.result() == [], (s, f.result())
+    return len(rec["runs"])
 
 
-def test_grid4096(bfs, grid4096):
-    g = grid4096
-    gh = upload(g)
-    srcs = graphgen.sources(g, 16)
-    lab, sizes = _component_sizes(g)
-    for i, s in enumerate(srcs[:3]):
-        say("grid4096 full parity source", s)
-        _, _, run, _ = check_single(g, gh, s, full_validate=(i == 0))
-        assert run["loop"] == bfs.BFS_LOOP_GRAPH and run["levels"] > 1000
-    rng = np.random.default_rng(1)
-    for s in srcs:
-        say("grid4096 sampled source", s)
-        d, p = gpu_bfs(gh, s)
-        run, _ = bfs.bfs_get_run_stats(gh)
-        assert run["reached"] == sizes[lab[s]] == int((d >= 0).sum())
-        _sampled_checks(g, s, d, p, rng, k=2000)
+CASES = [("rmat24", "bench", None), ("rmat24", "bench", "host"), ("rmat24", "default", None),
+         ("grid4096", "bench", None), ("grid4096", "bench", "host"), ("grid4096", "default", None),
+         ("rmat16", "bench", None), ("rmat16", "bench", "host"), ("rmat16", "default", None)]
+
+
+@pytest.mark.parametrize("name,config,loop", CASES, ids=[f"{a}-{b}-{c or 'graph'}" for a, b, c in CASES])
+def test_every_source(bfs, name, config, loop):
+    g, srcs, rp32, rec = workload(name)
+    if config == "bench":
+        gh, _ = bench.make_handle(bfs, g, rp32)
+    else:
+        gh = upload(g, bfs.BFS_ROWPTR32 if rp32 else 0)
+    info = bfs.bfs_graph_info_get(gh)
+    assert info["row_ptr_bytes"] == (4 if rp32 else 8) and info["nnz"] == g.nnz
+    if loop == "host":
+        bfs.bfs_set_params(gh, loop=bfs.BFS_LOOP_HOST, collect_timing=1)
+    say(name, config, loop or "graph", "params", bfs.bfs_get_params(gh))
+    # parents of every source in the benchmark's own configuration
+    with ThreadPoolExecutor(8) as pool:
+        done = run_all(bfs, g, gh, rec, parents=(config == "bench"), pool=pool)
+    assert done == len(srcs)
+    run, _ = bfs.bfs_get_run_stats(gh)
+    expect_loop = bfs.BFS_LOOP_HOST if loop == "host" else bfs.BFS_LOOP_GRAPH
+    assert run["loop"] == expect_loop
     gh.close()

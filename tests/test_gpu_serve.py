@@ -201,3 +201,50 @@ def test_destroy_graph_busy(bfs):
     bfs.bfs_serve_destroy(srv)
     if not closed:
         gh.close()
+
+
+def test_pool_at_full_size(bfs):
+    """The serving pool at its real sizes (12 graphs: RMAT 14-23, lattices up
+    to 2048^2, uniform random graphs of 2^20 vertices), created as the
+    benchmark creates them: 4 requests per graph through one server, first
+    one per graph alone, then all 48 interleaved under a budget that keeps
+    most batches waiting; every distance array equals the oracle's (SHA-256
+    digests written from the oracle) and parents form valid trees."""
+    import torch
+
+    import bench
+    from tests.gpu_util import check_graph_digest, golden, sha256
+    rec = golden()["pool"]
+    gs, handles = {}, {}
+    for kind, size in bench.SERVE_POOL:
+        name = f"{kind}{size}"
+        say("serve pool: generating", name)
+        g = bench._serve_graph(kind, size)
+        check_graph_digest(g, rec[name]["graph"])
+        gs[name] = g
+        handles[name] = bench.make_handle(bfs, g)[0]
+    reqs = [(name, r["source"], i % 2 == 0, r["dist_sha256"])
+            for i in range(4) for name in gs for r in rec[name]["runs"][i:i + 1]]
+
+    def verify(name, s, d, p, digest):
+        dn = d.cpu().numpy()
+        assert sha256(dn.astype("<i4")) == digest, f"{name} source {s}: distances differ from the oracle's"
+        if p is not None:
+            assert oracle.check_tree(gs[name], s, dn, p.cpu().numpy()) == [], (name, s)
+
+    largest = max(36 * g.n for g in gs.values())
+    srv = bfs.bfs_serve_create(largest + (256 << 20), 64)
+    say("serve pool: alone")
+    for name, s, wp, digest in reqs[:len(gs)]:
+        t, d, p = submit(bfs, srv, gs, handles, name, s, wp)
+        wait_all(bfs, srv, [t], timeout=120.0)
+        verify(name, s, d, p, digest)
+    say("serve pool: 48 requests interleaved")
+    outs = [submit(bfs, srv, gs, handles, name, s, wp) for name, s, wp, _ in reqs]
+    wait_all(bfs, srv, [t for t, _, _ in outs], timeout=120.0)
+    for (name, s, wp, digest), (t, d, p) in zip(reqs, outs):
+        verify(name, s, d, p, digest)
+    bfs.bfs_serve_destroy(srv)
+    torch.cuda.synchronize()
+    for h in handles.values():
+        h.close()

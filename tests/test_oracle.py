@@ -219,3 +219,54 @@ def test_mutants_are_caught(mutant, tmp_path):
 
 def test_unmutated_passes_pins():
     assert _pin_failures(oracle.load()) == []
+
+
+def test_check_tree_pins():
+    """check_tree (C) accepts valid BFS trees and names each planted fault:
+    a hand-built tree on a path, trees of the closed-form graphs, and the
+    corruptions the Python validator is pinned with."""
+    g, _ = graphs.path(6)
+    d = np.array([2, 1, 0, 1, 2, 3], np.int32)
+    assert oracle.check_tree(g, 2, d, np.array([1, 2, 2, 2, 3, 4], np.int32)) == []
+    assert oracle.check_tree(g, 2, d, np.array([1, 2, 1, 2, 3, 4], np.int32))[0].startswith("P1")
+    assert oracle.check_tree(g, 2, d, np.array([2, 2, 2, 2, 3, 4], np.int32))[0].startswith("P2: parent one")
+    # vertex 3 is one level above vertex 0 but not its neighbour
+    assert oracle.check_tree(g, 2, d, np.array([3, 2, 2, 2, 3, 4], np.int32))[0].startswith("P2: parent is a")
+    g2, _ = graphs.two_paths(4, 3)
+    d2, p2 = oracle.bfs(g2, 0)
+    assert oracle.check_tree(g2, 0, d2, p2) == []
+    p2b = p2.copy(); p2b[5] = 4
+    assert oracle.check_tree(g2, 0, d2, p2b)[0].startswith("P3")
+    p2c = p2.copy(); p2c[2] = -1
+    assert oracle.check_tree(g2, 0, d2, p2c)[0].startswith("P3")
+    for name, mk in graphs.CLOSED_FORMS.items():
+        gc, _ = mk()
+        dc, pc = oracle.bfs(gc, 0)
+        assert oracle.check_tree(gc, 0, dc, pc) == [], name
+    g = graphs.random_graph(400, 1200, 21)
+    s = 3
+    d, p = oracle.bfs(g, s)
+    assert oracle.check_tree(g, s, d, p) == []
+    v = int(np.flatnonzero(d > 0)[len(np.flatnonzero(d > 0)) // 2])
+    p_self = p.copy(); p_self[v] = v
+    assert oracle.check_tree(g, s, d, p_self) != []
+    same = int(np.flatnonzero(d == d[v])[0])
+    if same != p[v]:
+        p_same = p.copy(); p_same[v] = same
+        assert oracle.check_tree(g, s, d, p_same) != []
+    # one level up but not adjacent: only the row scan can catch it
+    up = [int(u) for u in np.flatnonzero(d == d[v] - 1)
+          if u not in set(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].tolist())]
+    if up:
+        p_far = p.copy(); p_far[v] = up[0]
+        errs = oracle.check_tree(g, s, d, p_far)
+        assert len(errs) == 1 and errs[0].startswith("P2: parent is a neighbour"), errs
+    p_out = p.copy(); p_out[v] = g.n
+    assert oracle.check_tree(g, s, d, p_out) != []
+    # agrees with the Python validator on random valid and corrupted trees
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        q = p.copy()
+        w = int(rng.integers(g.n))
+        q[w] = int(rng.integers(-1, g.n))
+        assert (oracle.check_tree(g, s, d, q) == []) == (oracle.validate(g, s, d, q) == [])
