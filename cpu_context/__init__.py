@@ -1,5 +1,6 @@
 """OpenMP versions of the paper's CPU kernels (Section 2: BFS-Conventional,
-BFS-Hybrid dagger, BFS-VisitedBitmap), timed on the host's cores as a
+BFS-NonAtomic, BFS-Hybrid with the 5 % rule, BFS-Hybrid dagger with the
+alpha/beta rule, BFS-VisitedBitmap), timed on the host's cores as a
 multicore context figure beside the GPU library and the serial oracle.
 
 Neither the oracle nor part of the GPU library: the benchmark reports it
@@ -21,7 +22,18 @@ _LIB = os.path.join(_HERE, "libbfs_omp.so")
 _lock = threading.Lock()
 _lib = None
 
-KINDS = {"conventional": 0, "hybrid": 1, "visited_bitmap": 2}
+# name: (top-down body, direction rule) of bfs_omp.c
+#   body 0 compare-and-swap on dist, 1 plain test and store of dist
+#   (duplicates allowed), 2 visited bitmap with atomic OR; rule 0 top-down
+#   only, 1 the 5 % frontier rule, 2 alpha/beta
+KINDS = {
+    "conventional": (0, 0),            # BFS-Conventional
+    "nonatomic": (1, 0),               # BFS-NonAtomic
+    "hybrid": (1, 1),                  # BFS-Hybrid: NonAtomic top-down body, 5 % rule
+    "hybrid_dagger": (1, 2),           # BFS-Hybrid dagger: alpha/beta rule
+    "visited_bitmap": (2, 1),          # BFS-VisitedBitmap: bitmap on BFS-Hybrid
+    "visited_bitmap_dagger": (2, 2),   # the bitmap with the alpha/beta rule
+}
 
 
 def build(force: bool = False) -> str:
@@ -41,26 +53,31 @@ def load():
         if _lib is None:
             lib = ctypes.CDLL(build())
             vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
-            lib.omp_bfs.argtypes = [i64, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
+            lib.omp_bfs.argtypes = [i64, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
             lib.omp_bfs.restype = i64
             _lib = lib
     return _lib
 
 
 def bfs(g, source: int, kind: str = "visited_bitmap", threads: int = 0, want_parent: bool = True,
-        alpha: int = 14, beta: int = 24):
-    """Runs one search; returns (dist, parent or None, seconds, levels).
-    `threads` = 0 uses OpenMP's default (OMP_NUM_THREADS or all cores)."""
+        alpha: int = 14, beta: int = 24, return_entries: bool = False):
+    """Runs one search; returns (dist, parent or None, seconds, levels), and
+    with return_entries also the frontier entries over all levels
+    (duplicates included).  `threads` = 0 uses OpenMP's default
+    (OMP_NUM_THREADS or all cores)."""
     lib = load()
+    body, rule = KINDS[kind]
     rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(g.col_idx, dtype=np.int32)
     dist = np.empty(g.n, dtype=np.int32)
     parent = np.empty(g.n, dtype=np.int32) if want_parent else None
     secs = ctypes.c_double()
-    levels = lib.omp_bfs(g.n, rp.ctypes.data, col.ctypes.data, int(source), KINDS[kind], int(alpha), int(beta),
+    entries = ctypes.c_int64()
+    levels = lib.omp_bfs(g.n, rp.ctypes.data, col.ctypes.data, int(source), body, rule, int(alpha), int(beta),
                          int(threads), dist.ctypes.data, parent.ctypes.data if want_parent else None,
-                         ctypes.byref(secs))
-    return dist, parent, secs.value, int(levels)
+                         ctypes.byref(secs), ctypes.byref(entries))
+    out = (dist, parent, secs.value, int(levels))
+    return out + (int(entries.value),) if return_entries else out
 
 
 def max_threads() -> int:
