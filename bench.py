@@ -421,28 +421,52 @@ def _component_edges(g):
     return per[lab]
 
 
-def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=6000):
+SERVE_CLASSES = {"rmat": "power-law (RMAT 14-23)", "grid": "lattice (512^2-2048^2)", "urand": "uniform random (2^20)"}
+
+
+def _pcts(lat_s):
+    return {"p50_ms": round(float(np.percentile(lat_s, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat_s, 99)) * 1e3, 3)}
+
+
+def bench_serving(bfs, torch, requests=2000, plain_fracs=(0.25, 0.5, 0.9), sat_fracs=(0.5, 0.9),
+                  budget=1 << 30, seed=6000):
     """Poisson arrivals over the 12-graph pool through the server, against
-    the same trace served first-come-first-served by plain bfs_run."""
-    graphs, handles, edges, nz = [], [], [], []
+    the same trace served first-come-first-served by plain bfs_run.
+
+    One trace of `requests` requests (graph Zipf(1.1), source uniform among
+    non-isolated vertices) is replayed at each rate: fractions of the plain
+    FCFS capacity C (the trace's requests per second of summed bfs_run
+    times, each request timed alone) and of the server's saturation rate S
+    (every request submitted at once).  At every rate the server is run for
+    real; the plain FCFS latencies are computed from the same requests'
+    measured bfs_run times (a single queue in arrival order), and at 0.9 C
+    the plain FCFS is also run for real (the host issues bfs_run at each
+    arrival).  The server's memory budget (`budget`, scratch of the batches
+    in flight; the graphs themselves are resident outside it) is smaller
+    than the pool's batches together, so admission waits for memory."""
+    graphs, handles, edges, nz, cls = [], [], [], [], []
     for kind, size in SERVE_POOL:
         g = _serve_graph(kind, size)
         graphs.append(g)
         handles.append(make_handle(bfs, g)[0])
         edges.append(_component_edges(g))
         nz.append(np.flatnonzero(g.degree > 0))
+        cls.append(kind)
     rng = np.random.default_rng(seed)
     zipf = 1.0 / np.arange(1, len(graphs) + 1) ** 1.1
     zipf /= zipf.sum()
     gid = rng.choice(len(graphs), size=requests, p=zipf)
     src = [int(nz[k][rng.integers(len(nz[k]))]) for k in gid]
+    gaps = rng.exponential(1.0, size=requests)  # unit-rate Poisson gaps, scaled per rate
     m_s = np.array([edges[k][s] for k, s in zip(gid, src)])
+    req_cls = np.array([cls[k] for k in gid])
     # output buffers: a pool per graph, reused once a request is done
     pool_size = 128
     bufs = [[torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(pool_size)] for g in graphs]
     torch.cuda.synchronize()
 
-    # plain first-come-first-served: each request's own run time, queued in order
+    # each request alone through bfs_run (the plain path's service times)
     dist = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
     for k in range(len(graphs)):
         bfs.bfs_run(handles[k], int(nz[k][0]), dist[k])
@@ -453,10 +477,11 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
     plain_rate = requests / run_s.sum()
 
     def serve(arrivals):
-        srv = bfs.bfs_serve_create(8 << 30, 64)
+        srv = bfs.bfs_serve_create(budget, 64)
         free = [list(range(pool_size)) for _ in graphs]
         inflight = {}
         lat = np.zeros(requests)
+        wait = np.zeros(requests)
         i = 0
         t0_ns = time.perf_counter_ns()  # CLOCK_MONOTONIC, as the server's timestamps
         t0 = t0_ns / 1e9
@@ -473,6 +498,7 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
                     j, b = inflight.pop(t)
                     # latency from the request's arrival time in the trace
                     lat[j] = (st["t_done_ns"] - t0_ns) / 1e9 - arrivals[j]
+                    wait[j] = (st["t_admit_ns"] - st["t_submit_ns"]) / 1e9
                     free[gid[j]].append(b)
                 elif state == bfs.BFS_REQ_FAILED:
                     raise RuntimeError("a served request failed")
@@ -480,31 +506,57 @@ def bench_serving(bfs, torch, requests=600, rates=(0.25, 0.5, 0.9, 1.5), seed=60
                 time.sleep(min(arrivals[i] - now, 0.001))
         wall = time.perf_counter() - t0
         bfs.bfs_serve_destroy(srv)
-        return lat, wall
+        return lat, wall, wait
 
-    # saturation: every request submitted at once
-    lat0, wall0 = serve(np.zeros(requests))
-    sat = requests / wall0
-    out = {"pool": [f"{k}{z}" for k, z in SERVE_POOL], "requests_per_rate": requests,
-           "saturation_rps": round(sat, 1), "plain_fcfs_capacity_rps": round(plain_rate, 1),
-           "saturation_gteps": round(m_s.sum() / wall0 / 1e9, 3), "rates": []}
-    for frac in rates:
-        rate = frac * sat
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=requests))
-        lat, wall = serve(arrivals)
-        # plain FCFS on the same trace (one request at a time, in arrival order)
+    def plain_model(arrivals):
         finish, fl = 0.0, np.empty(requests)
         for j in range(requests):
             finish = max(finish, arrivals[j]) + run_s[j]
             fl[j] = finish - arrivals[j]
-        out["rates"].append({
-            "rate_rps": round(rate, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-            "gteps": round(m_s.sum() / wall / 1e9, 3),
-            "plain_fcfs_p50_ms": round(float(np.percentile(fl, 50)) * 1e3, 3),
-            "plain_fcfs_p99_ms": round(float(np.percentile(fl, 99)) * 1e3, 3),
-            "plain_fcfs_gteps": round(m_s.sum() / max(finish, arrivals[-1]) / 1e9, 3)})
+        return fl, max(finish, arrivals[-1])
+
+    def plain_real(arrivals):
+        fl = np.empty(requests)
+        t0 = time.perf_counter()
+        for j in range(requests):
+            now = time.perf_counter() - t0
+            if arrivals[j] > now:
+                time.sleep(arrivals[j] - now)
+            bfs.bfs_run(handles[gid[j]], src[j], dist[gid[j]])
+            fl[j] = time.perf_counter() - t0 - arrivals[j]
+        return fl, time.perf_counter() - t0
+
+    def per_class(lat):
+        return {c: _pcts(lat[req_cls == c]) for c in SERVE_CLASSES if (req_cls == c).any()}
+
+    # saturation: every request submitted at once
+    lat0, wall0, _ = serve(np.zeros(requests))
+    sat = requests / wall0
+    out = {"pool": [f"{k}{z}" for k, z in SERVE_POOL], "requests_per_rate": requests,
+           "budget_bytes": budget, "classes": SERVE_CLASSES,
+           "requests_per_class": {c: int((req_cls == c).sum()) for c in SERVE_CLASSES},
+           "saturation_rps": round(sat, 1), "plain_fcfs_capacity_rps": round(plain_rate, 1),
+           "saturation_gteps": round(m_s.sum() / wall0 / 1e9, 3),
+           "alone_ms_per_class": {c: _pcts(run_s[req_cls == c]) for c in SERVE_CLASSES},
+           "rates": []}
+    for base, fracs, name in ((plain_rate, plain_fracs, "plain_capacity"), (sat, sat_fracs, "saturation")):
+        for frac in fracs:
+            rate = frac * base
+            arrivals = np.cumsum(gaps) / rate
+            lat, wall, wait = serve(arrivals)
+            fl, fwall = plain_model(arrivals)
+            row = {"rate_rps": round(rate, 1), "of": f"{frac} x {name}", **_pcts(lat),
+                   "p99_ms_per_class": per_class(lat),
+                   "admission_wait_p99_ms": round(float(np.percentile(wait, 99)) * 1e3, 3),
+                   "gteps": round(m_s.sum() / wall / 1e9, 3),
+                   "plain_fcfs_model": {**_pcts(fl), "p99_ms_per_class": per_class(fl),
+                                        "gteps": round(m_s.sum() / fwall / 1e9, 3)}}
+            if name == "plain_capacity" and frac == max(fracs):
+                rl, rwall = plain_real(arrivals)
+                row["plain_fcfs_run"] = {**_pcts(rl), "p99_ms_per_class": per_class(rl),
+                                         "gteps": round(m_s.sum() / rwall / 1e9, 3)}
+            out["rates"].append(row)
+            log(f"serving {row['of']}: {row['rate_rps']} rps p50 {row['p50_ms']} p99 {row['p99_ms']} ms")
     for h in handles:
         h.close()
     return out

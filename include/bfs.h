@@ -213,6 +213,12 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
  * server still holds requests on it). */
 int bfs_destroy_graph(bfs_graph_t g);
 
+/* Copies the device-resident CSR back to host memory, in the row order
+ * the device holds (with BFS_SORT_NEIGHBORS: each row hub-first, as the
+ * bottom-up levels scan it).  row_ptr_out: n+1 int64, col_idx_out: nnz int32
+ * (host pointers owned by the caller).  Errors: INVALID_ARG (null), DEVICE. */
+int bfs_graph_copy_csr(bfs_graph_t g, int64_t *row_ptr_out, int32_t *col_idx_out);
+
 /* Sets the HIP stream (a hipStream_t, passed as void*) on which runs of
  * this graph are issued.  NULL selects the null stream. */
 int bfs_graph_set_stream(bfs_graph_t g, void *hip_stream);

@@ -89,6 +89,7 @@ _SIGS = {
     "bfs_create_graph": ([_i64, _i64, _vp, _vp, _u32, _vp], ctypes.c_int),
     "bfs_destroy_graph": ([_vp], ctypes.c_int),
     "bfs_graph_set_stream": ([_vp, _vp], ctypes.c_int),
+    "bfs_graph_copy_csr": ([_vp, _vp, _vp], ctypes.c_int),
     "bfs_set_params": ([_vp, _vp], ctypes.c_int),
     "bfs_get_params": ([_vp, _vp], ctypes.c_int),
     "bfs_graph_info_get": ([_vp, _vp], ctypes.c_int),
@@ -211,6 +212,15 @@ def bfs_create_graph(row_ptr, col_idx, flags: int = 0) -> Graph:
 
 def bfs_destroy_graph(g: Graph):
     g.close()
+
+
+def bfs_graph_copy_csr(g: Graph):
+    """The device-resident CSR in its stored row order: (row_ptr int64[n+1],
+    col_idx int32[nnz]) numpy arrays."""
+    rp = np.empty(g.n + 1, np.int64)
+    col = np.empty(max(g.nnz, 1), np.int32)
+    _check(load_library().bfs_graph_copy_csr(g.handle, rp.ctypes.data, col.ctypes.data))
+    return rp, col[:g.nnz]
 
 
 def bfs_graph_set_stream(g: Graph, stream=None):

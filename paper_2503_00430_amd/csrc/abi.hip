@@ -379,7 +379,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
     return bail(fail(BFS_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(e)));
   {
     int rc = build_head(g);
-    if (!rc && (flags & BFS_SORT_NEIGHBORS)) rc = sort_neighbors_by_degree(g);
+    if (!rc && (flags & BFS_SORT_NEIGHBORS)) rc = sort_neighbors_by_degree(g, rp);
     if (rc) return bail(rc);
   }
   *out = g;
@@ -395,6 +395,22 @@ int bfs_destroy_graph(bfs_graph_t g) {
       return fail(BFS_ERR_BUSY, "graph still has %d requests in a server", g->server_refs.load());
   }
   destroy(g);
+  return BFS_OK;
+}
+
+int bfs_graph_copy_csr(bfs_graph_t g, int64_t *row_ptr_out, int32_t *col_idx_out) {
+  clear_error();
+  if (!g || !row_ptr_out || (g->nnz > 0 && !col_idx_out)) return fail(BFS_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(g->mu);
+  DeviceGuard dg(g->device);
+  if (g->rp64) {
+    BFS_HIP(hipMemcpy(row_ptr_out, g->rp, sizeof(int64_t) * (g->n + 1), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<int32_t> r32(g->n + 1);
+    BFS_HIP(hipMemcpy(r32.data(), g->rp, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost));
+    for (int64_t v = 0; v <= g->n; ++v) row_ptr_out[v] = r32[v];
+  }
+  if (g->nnz > 0) BFS_HIP(hipMemcpy(col_idx_out, g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost));
   return BFS_OK;
 }
 

@@ -188,7 +188,8 @@ struct DeviceGuard {
 
 int resolved_policy(const bfs_graph *g);
 int build_head(bfs_graph *g);  // fills g->head from the resident CSR
-int sort_neighbors_by_degree(bfs_graph *g);  // BFS_SORT_NEIGHBORS (reorder.hip)
+// BFS_SORT_NEIGHBORS (reorder.hip); host_rp: a host copy of the row offsets
+int sort_neighbors_by_degree(bfs_graph *g, const int64_t *host_rp);
 int alloc_single_scratch(bfs_graph *g);  // (re)allocates the large-vertex queues
 void release_graph_exec(bfs_graph *g);
 
