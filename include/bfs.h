@@ -263,6 +263,27 @@ int bfs_get_run_stats(bfs_graph_t g, bfs_run_stats *st, bfs_level_stats *levels,
  */
 int bfs_run_batch(bfs_graph_t g, const int32_t *sources, int32_t k, uint8_t *dist_out);
 
+/*
+ * bfs_run_batch_noalloc: bfs_run_batch for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).  The
+ * same search, with the same arguments, errors and output, but its scratch
+ * lives in a fixed array of BFS_NOALLOC_SCRATCH_BYTES that the library
+ * defines on every GPU it runs on (each GPU holds it until the process
+ * ends); the call itself allocates nothing.  The array holds three 64-bit
+ * source sets per vertex, eight distance bit planes per vertex when k >= 16,
+ * about nnz/64 bytes of queue and a 1 KiB control block, so with 16 or more
+ * sources a graph of up to about 1.5 million vertices fits (about 5 million
+ * with fewer); a larger one is refused with INVALID_ARG, naming the bytes it
+ * would need.  Every such call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (the search clears what it needs): the
+ * library serialises these calls within the process, and a caller must not
+ * run two of them concurrently from other code paths that bypass it.
+ * Synchronous.  Errors: INVALID_ARG (as bfs_run_batch, or the graph does not
+ * fit the array), DEVICE.
+ */
+#define BFS_NOALLOC_SCRATCH_BYTES (128u << 20)
+int bfs_run_batch_noalloc(bfs_graph_t g, const int32_t *sources, int32_t k, uint8_t *dist_out);
+
 /* Request states reported by bfs_serve_poll. */
 typedef enum bfs_req_state {
   BFS_REQ_QUEUED = 0,

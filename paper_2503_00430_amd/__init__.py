@@ -16,5 +16,6 @@ from ._lib import (  # noqa: F401
     BfsError, Graph, Server, library_path, load_library,
     bfs_create_graph, bfs_destroy_graph, bfs_graph_set_stream, bfs_graph_copy_csr, bfs_set_params, bfs_get_params,
     bfs_default_params, bfs_graph_info_get, bfs_run, bfs_get_run_stats, bfs_run_batch,
+    bfs_run_batch_noalloc, BFS_NOALLOC_SCRATCH_BYTES,
     bfs_serve_create, bfs_serve_destroy, bfs_serve_submit, bfs_serve_poll, bfs_last_error,
 )

@@ -96,6 +96,7 @@ _SIGS = {
     "bfs_run": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "bfs_get_run_stats": ([_vp, _vp, _vp, _i32], ctypes.c_int),
     "bfs_run_batch": ([_vp, _vp, _i32, _vp], ctypes.c_int),
+    "bfs_run_batch_noalloc": ([_vp, _vp, _i32, _vp], ctypes.c_int),
     "bfs_serve_create": ([ctypes.c_size_t, _i32, _vp], ctypes.c_int),
     "bfs_serve_destroy": ([_vp], ctypes.c_int),
     "bfs_serve_submit": ([_vp, _vp, _i32, _vp, _vp, _vp], ctypes.c_int),
@@ -287,6 +288,19 @@ def bfs_run_batch(g: Graph, sources, dist8):
     k = len(src)
     d = _dev_ptr(dist8, torch.uint8, k * g.n, "dist8")
     _check(load_library().bfs_run_batch(g.handle, src.ctypes.data, k, d))
+
+
+def bfs_run_batch_noalloc(g: Graph, sources, dist8):
+    """As bfs_run_batch, with the library's fixed scratch array (allocates
+    nothing on the device)."""
+    import torch
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = len(src)
+    d = _dev_ptr(dist8, torch.uint8, k * g.n, "dist8")
+    _check(load_library().bfs_run_batch_noalloc(g.handle, src.ctypes.data, k, d))
+
+
+BFS_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class Server:

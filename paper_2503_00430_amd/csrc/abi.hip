@@ -502,4 +502,18 @@ int bfs_run_batch(bfs_graph_t g, const int32_t *sources, int32_t k, uint8_t *dis
   return run_batch(g, sources, k, dist_out, nullptr);
 }
 
+int bfs_run_batch_noalloc(bfs_graph_t g, const int32_t *sources, int32_t k, uint8_t *dist_out) {
+  clear_error();
+  if (!g) return fail(BFS_ERR_INVALID_ARG, "null graph");
+  if (!sources || !dist_out) return fail(BFS_ERR_INVALID_ARG, "null argument");
+  if (k < 1 || k > 64) return fail(BFS_ERR_INVALID_ARG, "k = %d outside [1, 64]", k);
+  for (int i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n)
+      return fail(BFS_ERR_INVALID_ARG, "sources[%d] = %d outside [0, %lld)", i, sources[i],
+                  (long long)g->n);
+  std::lock_guard<std::mutex> lk(g->mu);
+  DeviceGuard dg(g->device);
+  return run_batch_static(g, sources, k, dist_out);
+}
+
 }  // extern "C"

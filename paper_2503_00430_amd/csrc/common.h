@@ -199,6 +199,9 @@ int run_single(bfs_graph *g, int32_t source, int32_t *dist, int32_t *parent);
 // Batched search (msbfs.hip).  `stream` overrides the graph's stream when
 // not null.  Writes k rows of uint8 distances.
 int run_batch(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t stream);
+// The same search with its scratch in the library's fixed per-device array
+// (bfs_run_batch_noalloc): allocates nothing.
+int run_batch_static(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8);
 
 }  // namespace bfsmi
 

@@ -30,6 +30,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "device_util.h"
@@ -50,7 +51,6 @@ namespace {
 struct MsCtl {
   int32_t levels;  // levels run (for the caller; the kernel keeps its own count)
   int32_t pad;
-  int32_t src[64];
   unsigned long long hcnt[2];
   alignas(128) unsigned long long acc[3][16];  // [0] new pairs, [1] frontier edges, [2] OR of new bits
 };
@@ -74,6 +74,7 @@ struct MsArgs {
   uint64_t *hq;      // chunk queue of the rows longer than kMsChunk: chunk << 32 | v
   int64_t hq_cap;
   uint64_t *planes;  // [8][n] distance bit planes, or null: rows written per level
+  int32_t src[64];   // the k sources (passed by value: no copy to the device first)
 };
 
 constexpr int kMsPlaneMinK = 16;
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   }
   grid.sync();
   if (tid < A.k) {
-    const int32_t s = c->src[tid];
+    const int32_t s = A.src[tid];
     const unsigned long long bit = 1ull << tid;
     atomicOr(reinterpret_cast<unsigned long long *>(A.seen + s), bit);
     const uint64_t was = atomicOr(reinterpret_cast<unsigned long long *>(A.front + s), bit);
@@ -387,12 +388,21 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs<RowT> A) {
   }
 }
 
+// Where one batched search keeps its scratch.
+struct MsView {
+  uint64_t *seen, *front, *next, *hq, *planes;
+  MsCtl *ctl;
+  int64_t hq_cap;
+};
+
+// Every queued row has more than kMsChunk edges and enters a level's
+// frontier once, so a level has fewer than 2 nnz / kMsChunk chunks.
+int64_t ms_hq_cap(const bfs_graph *g) { return 2 * (g->nnz / kMsChunk) + 64; }
+
 int ensure_ms_scratch(bfs_graph *g) {
   if (g->ms.seen) return BFS_OK;
   const size_t words = (size_t)g->n;
-  // every queued row has more than kMsChunk edges and enters a level's
-  // frontier once, so a level has fewer than 2 nnz / kMsChunk chunks
-  const int64_t hq_cap = 2 * (g->nnz / kMsChunk) + 64;
+  const int64_t hq_cap = ms_hq_cap(g);
   void *p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t sizes[6] = {words * 8, words * 8, words * 8, kMsCtlBytes,
                            (size_t)hq_cap * 8, 8 * words * 8};
@@ -414,29 +424,25 @@ int ensure_ms_scratch(bfs_graph *g) {
 }
 
 template <class RowT>
-int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t st) {
-  int rc = ensure_ms_scratch(g);
-  if (rc) return rc;
+int batch_impl(bfs_graph *g, const MsView &V, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t st) {
   MsArgs<RowT> A;
   A.rp = static_cast<const RowT *>(g->rp);
   A.col = g->col;
   A.n = g->n;
   A.nnz = g->nnz;
-  A.seen = g->ms.seen;
-  A.front = g->ms.front;
-  A.next = g->ms.next;
+  A.seen = V.seen;
+  A.front = V.front;
+  A.next = V.next;
   A.dist8 = dist8;
-  A.hq = g->ms.hq;
-  A.hq_cap = g->ms.hq_cap;
-  A.planes = k >= kMsPlaneMinK ? g->ms.planes : nullptr;
-  A.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
+  A.hq = V.hq;
+  A.hq_cap = V.hq_cap;
+  A.planes = k >= kMsPlaneMinK ? V.planes : nullptr;
+  A.ctl = V.ctl;
   A.k = k;
   A.bu_percent = g->params.msbfs_bu_percent;
   A.heavy = kWave;
   A.aligned4 = (reinterpret_cast<uintptr_t>(dist8) & 3) == 0;
-  // sources go straight into the control block
-  BFS_HIP(hipMemcpyAsync(reinterpret_cast<char *>(A.ctl) + offsetof(MsCtl, src), sources,
-                         sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+  for (int i = 0; i < 64; ++i) A.src[i] = i < k ? sources[i] : 0;
   const int bs = g->params.msbfs_block_size;
   int per_cu = 0, cus = 0;
   BFS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_msbfs<RowT>, bs, 0));
@@ -450,12 +456,80 @@ int batch_impl(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, 
   return BFS_OK;
 }
 
+// Scratch of the allocation-free batched search: one file-scope device
+// array per GPU, kept by the process until it ends.  Host code never uses
+// the array's name as an address (on the host it names a stand-in, not
+// device memory): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is kept per device.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu[kMaxDevices];  // one search at a time per device uses its array
+void *g_static_ptr[kMaxDevices];      // its device address, once taken (under the lock)
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the static array a batch of k searches on g uses (the layout of
+// static_view).
+size_t static_scratch_bytes(const bfs_graph *g, int32_t k) {
+  const size_t sets = round256((size_t)g->n * 8);
+  size_t b = 3 * sets + round256(kMsCtlBytes) + round256((size_t)ms_hq_cap(g) * 8);
+  if (k >= kMsPlaneMinK) b += 8 * sets;
+  return b;
+}
+
+MsView static_view(const bfs_graph *g, uint8_t *base, int32_t k) {
+  const size_t sets = round256((size_t)g->n * 8);
+  MsView V;
+  size_t off = 0;
+  V.seen = reinterpret_cast<uint64_t *>(base + off), off += sets;
+  V.front = reinterpret_cast<uint64_t *>(base + off), off += sets;
+  V.next = reinterpret_cast<uint64_t *>(base + off), off += sets;
+  V.ctl = reinterpret_cast<MsCtl *>(base + off), off += round256(kMsCtlBytes);
+  V.hq = reinterpret_cast<uint64_t *>(base + off), off += round256((size_t)ms_hq_cap(g) * 8);
+  V.hq_cap = ms_hq_cap(g);
+  V.planes = k >= kMsPlaneMinK ? reinterpret_cast<uint64_t *>(base + off) : nullptr;
+  return V;
+}
+
 }  // namespace
 
 int run_batch(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8, hipStream_t stream) {
   hipStream_t st = stream ? stream : g->stream;
-  return g->rp64 ? batch_impl<int64_t>(g, sources, k, dist8, st)
-                 : batch_impl<int32_t>(g, sources, k, dist8, st);
+  int rc = ensure_ms_scratch(g);
+  if (rc) return rc;
+  MsView V;
+  V.seen = g->ms.seen;
+  V.front = g->ms.front;
+  V.next = g->ms.next;
+  V.hq = g->ms.hq;
+  V.hq_cap = g->ms.hq_cap;
+  V.planes = g->ms.planes;
+  V.ctl = reinterpret_cast<MsCtl *>(g->ms.counters);
+  return g->rp64 ? batch_impl<int64_t>(g, V, sources, k, dist8, st)
+                 : batch_impl<int32_t>(g, V, sources, k, dist8, st);
+}
+
+int run_batch_static(bfs_graph *g, const int32_t *sources, int32_t k, uint8_t *dist8) {
+  const size_t need = static_scratch_bytes(g, k);
+  if (need > kStaticScratchBytes)
+    return fail(BFS_ERR_INVALID_ARG,
+                "the graph needs %zu bytes of batch scratch for k = %d; the allocation-free entry point "
+                "holds %zu (use bfs_run_batch)", need, k, kStaticScratchBytes);
+  if (g->device < 0 || g->device >= kMaxDevices)
+    return fail(BFS_ERR_INVALID_ARG, "device %d beyond the %d the library tracks", g->device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_static_mu[g->device]);
+  if (!g_static_ptr[g->device]) {  // first call on this device (which is current)
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BFS_ERR_DEVICE, "hipGetSymbolAddress of the batch scratch failed: %s", hipGetErrorString(e));
+    g_static_ptr[g->device] = p;
+  }
+  const MsView V = static_view(g, static_cast<uint8_t *>(g_static_ptr[g->device]), k);
+  return g->rp64 ? batch_impl<int64_t>(g, V, sources, k, dist8, g->stream)
+                 : batch_impl<int32_t>(g, V, sources, k, dist8, g->stream);
 }
 
 }  // namespace bfsmi
