@@ -82,6 +82,12 @@ constexpr size_t kAccOffset = (size_t)kMaxBlocks * kPartials;
 constexpr size_t kArriveOffset = kAccOffset + (size_t)kArriveGroups * kPartials * kLineU64;
 constexpr size_t kPartialsAlloc = kArriveOffset + (size_t)(kArriveGroups + 1) * kLineU64;
 
+// Occupancy summaries of the frontier bitmaps: at most this many bits
+// (32 KB, copied into each bottom-up workgroup's LDS), and at most 8 bitmap
+// words per bit (a bottom-up wavefront stores whole summary bytes).
+constexpr int64_t kSumMaxBits = (int64_t)1 << 18;
+constexpr int kSumMaxShift = 3;
+
 // Everything a single-source kernel needs, passed by value.
 template <class RowT>
 struct DevG {
@@ -93,6 +99,10 @@ struct DevG {
   const uint32_t *hrank;  // per word: non-isolated vertices in the words before it
   uint64_t *vis;        // visited bitmap
   uint64_t *bm[2];      // frontier bitmaps (current / next alternate)
+  uint64_t *sm[2];      // their occupancy summaries: bit i set if words [i << sshift,
+                        // (i + 1) << sshift) of bm[b] may hold a set bit (a superset)
+  int32_t sshift;       // log2 of the bitmap words per summary bit (-1: no summaries)
+  int32_t swords;       // 64-bit words per summary
   int32_t *qs[2];       // queue sets: small-degree vertices
   int32_t *qm[2];       //             medium-degree vertices
   uint64_t *ql[2];      //             large-degree vertices, one entry per chunk: chunk << 32 | v
@@ -133,6 +143,9 @@ struct bfs_graph {
   uint32_t *hrank = nullptr;  // per word: count of non-isolated vertices in earlier words
   uint64_t *vis = nullptr;
   uint64_t *bm[2] = {nullptr, nullptr};
+  uint64_t *sm[2] = {nullptr, nullptr};  // occupancy summaries of bm (see DevG)
+  int32_t sshift = -1;
+  int64_t swords = 0;
   int32_t *qs[2] = {nullptr, nullptr};
   int32_t *qm[2] = {nullptr, nullptr};
   uint64_t *ql[2] = {nullptr, nullptr};

@@ -26,6 +26,17 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long x) {
   return x;
 }
 
+// The global-memory view of a device pointer whose address space the
+// compiler cannot see (one loaded from memory, such as the output arrays in
+// the control block).  Accesses through a plain pointer of that kind become
+// flat instructions, which also count as LDS operations, so every later wait
+// for an LDS access would wait for them too; through this view they are
+// global loads and stores.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 // Workgroup order that gives each XCD a contiguous range of workgroups
 // (consecutive workgroup ids are dealt round-robin to the 8 XCDs).
 __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {

@@ -274,8 +274,8 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
   for (int64_t i = tid; i < G.n; i += stride) {
     // streaming stores: left dirty in the caches, these lines would be
     // written back during the first dense level and slow it (-5 % per search)
-    __builtin_nontemporal_store((i == s) ? 0 : -1, dist + i);
-    if (parent) __builtin_nontemporal_store((i == s) ? s : -1, parent + i);
+    __builtin_nontemporal_store((i == s) ? 0 : -1, gptr(dist + i));
+    if (parent) __builtin_nontemporal_store((i == s) ? s : -1, gptr(parent + i));
   }
   const int64_t sw = s >> 6;
   const uint64_t sb = 1ull << (s & 63);
@@ -284,6 +284,13 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     // hybrid searches keep bm[0] as the current frontier bitmap from level 0
     G.bm[0][w] = (policy != BFS_POLICY_TD_ONLY && w == sw) ? sb : 0ull;
     G.bm[1][w] = 0;
+  }
+  if (G.sshift >= 0) {  // summaries: bm[0]'s holds the source's word
+    const int64_t sb = sw >> G.sshift;
+    for (int64_t w = tid; w < G.swords; w += stride) {
+      G.sm[0][w] = (policy != BFS_POLICY_TD_ONLY && w == (sb >> 6)) ? 1ull << (sb & 63) : 0ull;
+      G.sm[1][w] = 0;
+    }
   }
   for (int64_t i = tid; i < (int64_t)kPartialsAlloc; i += stride) G.partials[i] = 0;  // and arrivals
   if (tid == 0) {
@@ -463,12 +470,34 @@ __device__ void reduce_partials(unsigned long long *partials, int nblocks, unsig
 // levels: an expanded vertex leaves it, a discovered one enters it (the two
 // sets are disjoint, and atomics on shared words commute), so a switch to
 // bottom-up needs no conversion.  `fbm` is null for top-down-only searches.
-__device__ __forceinline__ void fbm_set(uint64_t *fbm, int32_t v) {
-  if (fbm) atomicOr(reinterpret_cast<unsigned long long *>(fbm + (v >> 6)), 1ull << (v & 63));
+// A vertex entering the bitmap also sets its word's bit in the bitmap's
+// occupancy summary (`fsm`, null when the graph has none); bits leaving the
+// bitmap leave the summary as it is, so it stays a superset of the occupied
+// words until a bottom-up level rewrites it exactly.
+__device__ __forceinline__ void fbm_set(uint64_t *fbm, uint64_t *fsm, int32_t sshift, int32_t v) {
+  if (fbm) {
+    atomicOr(reinterpret_cast<unsigned long long *>(fbm + (v >> 6)), 1ull << (v & 63));
+    if (fsm) {
+      const uint32_t sb = ((uint32_t)v >> 6) >> sshift;
+      atomicOr(reinterpret_cast<unsigned long long *>(fsm + (sb >> 6)), 1ull << (sb & 63));
+    }
+  }
 }
 __device__ __forceinline__ void fbm_clear(uint64_t *fbm, int32_t u) {
   if (fbm) atomicAnd(reinterpret_cast<unsigned long long *>(fbm + (u >> 6)), ~(1ull << (u & 63)));
 }
+
+// Level state a top-down level needs, read once per level.
+struct TdLevel {
+  int32_t qcur, level;
+  int64_t cnt[3];
+  int64_t m_f;         // degree sum of the frontier (steers the medium-row split)
+  int32_t *dist, *parent;
+  uint64_t *fbm;       // current frontier bitmap (hybrid searches), else null
+  uint64_t *fsm;       // its occupancy summary (null: none)
+  int32_t sshift;      // bitmap words per summary bit, log2
+  bool from_bitmap;    // the frontier is the bitmap of a bottom-up level
+};
 
 // Levels whose frontier has fewer edges than this claim with the atomic
 // alone: reading the visited word first saves the atomics on vertices
@@ -477,10 +506,12 @@ __device__ __forceinline__ void fbm_clear(uint64_t *fbm, int32_t u) {
 constexpr int64_t kPreloadMinEdges = 65536;
 
 template <class RowT>
-__device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, int32_t level,
-                                         int32_t *dist, int32_t *parent, uint64_t *fbm, bool has, int32_t u,
-                                         int32_t v, bool preload, unsigned long long &nfound,
-                                         unsigned long long &dfound) {
+__device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, int qn, const TdLevel &T,
+                                         bool has, int32_t u, int32_t v, bool preload,
+                                         unsigned long long &nfound, unsigned long long &dfound) {
+  const int32_t level = T.level;
+  int32_t *dist = T.dist;
+  int32_t *parent = T.parent;
   bool win = false;
   int64_t deg = 0;
   bool claimed = false;
@@ -494,14 +525,14 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
       }
     }
     else if (G.td_visited == BFS_TD_DIST_CAS) claimed = atomicCAS(dist + v, -1, level + 1) == -1;
-    else claimed = dist[v] < 0;  // plain test: racing discoverers may all pass
+    else claimed = *gptr(dist + v) < 0;  // plain test: racing discoverers may all pass
   }
   if (claimed) {
     win = true;
     // (streaming stores, plain: every writer of v stores this same value)
-    __builtin_nontemporal_store(level + 1, dist + v);
-    if (parent) __builtin_nontemporal_store(u, parent + v);
-    fbm_set(fbm, v);
+    __builtin_nontemporal_store(level + 1, gptr(dist + v));
+    if (parent) __builtin_nontemporal_store(u, gptr(parent + v));
+    fbm_set(T.fbm, T.fsm, T.sshift, v);
     deg = G.head[v].x;
     nfound += 1;
     dfound += (unsigned long long)deg;
@@ -518,16 +549,6 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
 //   the rest                      workgroup per t2-edge chunk of a larger
 //                                 vertex.
 
-// Level state a top-down level needs, read once per level.
-struct TdLevel {
-  int32_t qcur, level;
-  int64_t cnt[3];
-  int64_t m_f;         // degree sum of the frontier (steers the medium-row split)
-  int32_t *dist, *parent;
-  uint64_t *fbm;       // current frontier bitmap (hybrid searches), else null
-  bool from_bitmap;    // the frontier is the bitmap of a bottom-up level
-};
-
 template <class RowT>
 __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl *c) {
   TdLevel t;
@@ -543,6 +564,8 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
   t.dist = c->dist;
   t.parent = c->parent;
   t.fbm = c->policy != BFS_POLICY_TD_ONLY ? (c->bcur ? G.bm[1] : G.bm[0]) : nullptr;
+  t.fsm = (t.fbm && G.sshift >= 0) ? (c->bcur ? G.sm[1] : G.sm[0]) : nullptr;
+  t.sshift = G.sshift;
   t.from_bitmap = c->conv == kConvB2Q;
   return t;
 }
@@ -582,7 +605,7 @@ __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage 
   } else {  // Section 2, BFS-NonAtomic (either form): a plain test, duplicates allowed
     int32_t d[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) d[k] = x[k] >= 0 ? T.dist[x[k]] : 0;
+    for (int k = 0; k < K; ++k) d[k] = x[k] >= 0 ? *gptr(T.dist + x[k]) : 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) win[k] = x[k] >= 0 && d[k] < 0;
   }
@@ -593,9 +616,9 @@ __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage 
   for (int k = 0; k < K; ++k) {
     if (win[k]) {
       // streaming stores, plain: every writer of x[k] stores this same value
-      __builtin_nontemporal_store(T.level + 1, T.dist + x[k]);
-      if (T.parent) __builtin_nontemporal_store(u[k], T.parent + x[k]);
-      fbm_set(T.fbm, x[k]);
+      __builtin_nontemporal_store(T.level + 1, gptr(T.dist + x[k]));
+      if (T.parent) __builtin_nontemporal_store(u[k], gptr(T.parent + x[k]));
+      fbm_set(T.fbm, T.fsm, T.sshift, x[k]);
       nfound += 1;
       dfound += (unsigned long long)dv[k];
     }
@@ -616,7 +639,7 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
   for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
     const bool has = j < deg;
     const int32_t v = has ? G.col[row0 + j] : 0;
-    td_visit(G, S, qn, T.level, T.dist, T.parent, T.fbm, has, u, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
+    td_visit(G, S, qn, T, has, u, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
   }
 }
 
@@ -768,7 +791,7 @@ __device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLev
     int32_t du = -1;
     if (act) {
       u = ring[(head + lane) & (kCandTd - 1)];
-      du = T.dist[u];
+      du = *gptr(T.dist + u);
       h = G.head[u];
       row0 = (int64_t)G.rp[u];
     }
@@ -787,7 +810,7 @@ __device__ __forceinline__ void td_level_bitmap(const DevG<RowT> &G, const TdLev
         const int64_t j = b + lane;
         const bool has = j < end;
         const int32_t v = has ? G.col[j] : 0;
-        td_visit(G, S, qn, T.level, T.dist, T.parent, fbm, has, ub, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
+        td_visit(G, S, qn, T, has, ub, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
       }
     }
   };
@@ -950,6 +973,8 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
     T.fbm = nullptr;  // top-down only: no frontier bitmap to keep
+    T.fsm = nullptr;
+    T.sshift = G.sshift;
     T.m_f = INT64_MAX;  // every workgroup takes part anyway: always split long medium rows
     T.from_bitmap = false;
     const Stage S = stage_open(lds);
@@ -1018,8 +1043,34 @@ struct BuWaveLds {
 
 __host__ __device__ constexpr size_t bu_lds_bytes(int bs) { return (size_t)(bs / kWave) * sizeof(BuWaveLds); }
 
-__device__ __forceinline__ bool front_bit(const uint32_t *front, int32_t x) {
-  return (front[x >> 5] >> (x & 31)) & 1u;
+// A bottom-up level copies the frontier summary into LDS when the frontier
+// has at most this many vertices per bitmap word.
+constexpr int64_t kSumFrontierWords = 2;
+
+// The frontier bitmap a bottom-up level tests, and optionally an LDS copy
+// of its occupancy summary: a neighbour whose word's summary bit is clear is
+// not in the frontier, and is rejected without the random read of its
+// frontier word (with a small frontier, most of the level's reads).
+struct Front {
+  const uint32_t *bits;  // the frontier bitmap as 32-bit words
+  const uint64_t *lsum;  // the summary in LDS, or null (test every neighbour's word)
+  int32_t sshift;
+};
+
+__device__ __forceinline__ bool may_be_front(const Front &F, int32_t x) {
+  if (!F.lsum) return true;
+  const uint32_t sb = ((uint32_t)x >> 6) >> F.sshift;
+  return (F.lsum[sb >> 6] >> (sb & 63)) & 1ull;
+}
+
+// The frontier word holding vertex x (x >= 0), or 0 where the summary rules
+// it out.
+__device__ __forceinline__ uint32_t front_word(const Front &F, int32_t x) {
+  return may_be_front(F, x) ? F.bits[x >> 5] : 0u;
+}
+
+__device__ __forceinline__ bool front_bit(const Front &F, int32_t x) {
+  return (front_word(F, x) >> (x & 31)) & 1u;
 }
 
 // Per-lane counters of a bottom-up level (a lane handles far fewer than
@@ -1029,53 +1080,108 @@ struct BuCount {
   unsigned long long fdeg = 0, exam = 0;
 };
 
-// Scans `cnt` (<= 64) deferred rows starting at ring slot `head`, one per
-// lane (rows longer than tbu by the whole wavefront); records the finds.
+// Records a bottom-up find: v's distance and parent (streaming stores: the
+// level does not read them again, and left in the caches they would take
+// room from the frontier words and head records), its counts, and its bit
+// in the run's found masks.
+template <class RowT>
+__device__ __forceinline__ void bu_found(BuWaveLds &W, int32_t v, int32_t deg, int32_t hit, int64_t sr,
+                                         int32_t level, int32_t *dist, int32_t *parent, BuCount &C) {
+  __builtin_nontemporal_store(level + 1, gptr(dist + v));
+  if (parent) __builtin_nontemporal_store(hit, gptr(parent + v));
+  C.found += 1;
+  C.fdeg += (unsigned long long)deg;
+  atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[(v >> 6) - sr]), 1ull << (v & 63));
+}
+
+// Scans the rows of the `cnt` (<= 64) deferred vertices from ring slot
+// `head` past their head records.  The rows' remaining neighbours are laid
+// end to end and read 64 at a time, a lane per neighbour, so a step reads
+// whole stretches of rows whatever their lengths (one row per lane would take
+// as many steps as the longest row needs while the other lanes idle).  Each
+// row takes its first frontier neighbour in row order; lanes of a row that
+// has already hit read nothing more.  Records the finds.
 template <class RowT>
 __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsigned head, unsigned cnt,
-                                         const uint32_t *front, int64_t sr, int32_t level, int32_t *dist,
+                                         const Front &front, int64_t sr, int32_t level, int32_t *dist,
                                          int32_t *parent, BuCount &C) {
   const int lane = lane_id();
   const bool act = (unsigned)lane < cnt;
   const unsigned slot = (head + lane) & (kDefer - 1);
   int32_t v = 0, deg = 0;
-  int64_t row0 = 0;
+  int64_t from = 0;  // the row's first neighbour past the head record
   if (act) {
     v = W.dv[slot];
     deg = W.ddeg[slot];
-    row0 = (int64_t)G.rp[v];
+    from = (int64_t)G.rp[v] + 3;
   }
-  const bool heavy = act && deg > G.tbu;
+  const int32_t len = act ? deg - 3 : 0;  // >= 1: deferred rows are longer than the head
+  int32_t incl = len;  // inclusive prefix sum of the lengths over the lanes
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const int32_t off = incl - len;  // the row's first position in the packed sequence
+  const int32_t total = __shfl(incl, kWave - 1);
+  bool found = false;
+  int32_t hit = -1, ex = deg;
+  const uint64_t upto = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;  // lanes <= this one
+  for (int32_t p = 0; p < total; p += kWave) {  // uniform
+    // position p + lane belongs to the last row that starts at or before it
+    const bool starts = act && off >= p && off < p + kWave;
+    const uint64_t sbits = wave_or(starts ? 1ull << (off - p) : 0ull);
+    const int r = __popcll(__ballot(act && off < p)) + __popcll(sbits & upto) - 1;
+    const int32_t e = p + lane;
+    const int64_t rfrom = __shfl(from, r);
+    const int32_t roff = __shfl(off, r);
+    const bool rdone = __shfl((int)found, r) != 0;
+    int32_t x = -1;
+    bool h = false;
+    if (e < total && !rdone) {
+      x = G.col[rfrom + (e - roff)];
+      h = front_bit(front, x);
+    }
+    const uint64_t hm = __ballot(h);
+    // each unfinished row takes the first hit within its own lanes
+    int f = -1;
+    if (act && !found) {
+      const int32_t lo = max(off, p) - p, hi = min(off + len, p + kWave) - p;  // its lanes [lo, hi)
+      if (lo < hi) {
+        const uint64_t seg = (hi == kWave ? ~0ull : (1ull << hi) - 1) & ~((1ull << lo) - 1);
+        const uint64_t mh = hm & seg;
+        if (mh) f = __builtin_ctzll(mh);
+      }
+    }
+    const int32_t xf = __shfl(x, f < 0 ? 0 : f);
+    if (f >= 0) {
+      found = true;
+      hit = xf;
+      ex = 3 + (p + f - off) + 1;
+    }
+  }
+  if (act) C.exam += (unsigned long long)ex;
+  if (found) bu_found<RowT>(W, v, deg, hit, sr, level, dist, parent, C);
+}
+
+// Scans the rows of the lanes in `lanes` (vertices longer than tbu) one
+// after the other, each by the whole wavefront 64 neighbours at a time past
+// its head record, stopping at the row's first frontier neighbour.  Records
+// the finds.
+template <class RowT>
+__device__ __forceinline__ void bu_long_rows(const DevG<RowT> &G, BuWaveLds &W, uint64_t lanes, int32_t v,
+                                             int32_t deg, const Front &front, int64_t sr, int32_t level,
+                                             int32_t *dist, int32_t *parent, BuCount &C) {
+  const int lane = lane_id();
+  const bool mine = (lanes >> lane) & 1ull;
+  int64_t row0 = 0;
+  if (mine) row0 = (int64_t)G.rp[v];
   bool found = false;
   int32_t hit = -1;
   int64_t ex = deg;
-  if (act && !heavy) {
-    const int64_t end = row0 + deg;
-    for (int64_t j0 = row0 + 3; j0 < end; j0 += kBuUnroll) {
-      int32_t x[kBuUnroll];
-      uint32_t f[kBuUnroll];
-#pragma unroll
-      for (int q = 0; q < kBuUnroll; ++q) x[q] = (j0 + q < end) ? G.col[j0 + q] : -1;
-#pragma unroll
-      for (int q = 0; q < kBuUnroll; ++q) f[q] = (x[q] >= 0) ? front[x[q] >> 5] : 0u;
-      int first = -1;
-#pragma unroll
-      for (int q = kBuUnroll - 1; q >= 0; --q)
-        if (x[q] >= 0 && ((f[q] >> (x[q] & 31)) & 1u)) first = q;
-      if (first >= 0) {
-        found = true;
-#pragma unroll
-        for (int q = 0; q < kBuUnroll; ++q)
-          if (q == first) hit = x[q];
-        ex = j0 - row0 + first + 1;
-        break;
-      }
-    }
-  }
-  uint64_t hm = __ballot(heavy);
-  while (hm) {
-    const int l = __ffsll((unsigned long long)hm) - 1;
-    hm &= hm - 1;
+  while (lanes) {
+    const int l = __ffsll((unsigned long long)lanes) - 1;
+    lanes &= lanes - 1;
     const int64_t r0 = __shfl(row0, l);
     const int64_t e0 = r0 + __shfl(deg, l);
     int64_t exl = e0 - r0;
@@ -1104,23 +1210,18 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
       }
     }
   }
-  if (act) C.exam += (unsigned long long)ex;
-  if (found) {
-    __builtin_nontemporal_store(level + 1, dist + v);
-    if (parent) __builtin_nontemporal_store(hit, parent + v);
-    C.found += 1;
-    C.fdeg += (unsigned long long)deg;
-    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[(v >> 6) - sr]), 1ull << (v & 63));
-  }
+  if (mine) C.exam += (unsigned long long)ex;
+  if (found) bu_found<RowT>(W, v, deg, hit, sr, level, dist, parent, C);
 }
 
 // Resolves one batch of `cnt` candidates (lane < cnt holds vertex v with
-// head record h): tests the head neighbours, records the finds, defers the
-// rest of the longer rows (draining 64 deferred rows when that many wait,
-// and every deferred row after the `last` batch of a run).
+// head record h): tests the head neighbours, records the finds, scans rows
+// longer than tbu at once and defers the rest of the longer rows (draining
+// 64 deferred rows when that many wait, and every deferred row after the
+// `last` batch of a run).
 template <class RowT>
 __device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, int32_t v, const int4 h, int cnt,
-                                           const uint32_t *front, int64_t sr, int32_t level, int32_t *dist,
+                                           const Front &front, int64_t sr, int32_t level, int32_t *dist,
                                            int32_t *parent, unsigned &dh, unsigned &dc, bool last, BuCount &C) {
   const int lane = lane_id();
   const bool act = lane < cnt;
@@ -1128,12 +1229,12 @@ __device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, in
   // misses (with hub-first rows most finds are at the first, and the
   // frontier-bit gathers are the level's largest request count)
   uint32_t f0 = 0, f1 = 0, f2 = 0;
-  if (act) f0 = front[h.y >> 5];  // degree >= 1: the first neighbour exists
+  if (act) f0 = front_word(front, h.y);  // degree >= 1: the first neighbour exists
   if (act && !((f0 >> (h.y & 31)) & 1u)) {
-    if (h.z >= 0) f1 = front[h.z >> 5];
-    if (h.w >= 0) f2 = front[h.w >> 5];
+    if (h.z >= 0) f1 = front_word(front, h.z);
+    if (h.w >= 0) f2 = front_word(front, h.w);
   }
-  bool found = false, defer = false;
+  bool found = false, defer = false, longrow = false;
   int32_t hit = -1;
   if (act) {
     int32_t ex = h.x;
@@ -1144,21 +1245,14 @@ __device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, in
     } else if (h.w >= 0 && ((f2 >> (h.w & 31)) & 1u)) {
       found = true; hit = h.w; ex = 3;
     } else if (h.x > 3) {
-      defer = true;  // counted when its row is scanned
+      (h.x > G.tbu ? longrow : defer) = true;  // counted when its row is scanned
     }
-    if (!defer) C.exam += (unsigned long long)ex;
+    if (!defer && !longrow) C.exam += (unsigned long long)ex;
     C.scan += 1;
   }
-  if (found) {
-    // streaming stores: the level's distance and parent lines are not read
-    // again here, and keeping them out of the caches leaves room for the
-    // frontier-bit and head-record lines (-2.5 % per search)
-    __builtin_nontemporal_store(level + 1, dist + v);
-    if (parent) __builtin_nontemporal_store(hit, parent + v);
-    C.found += 1;
-    C.fdeg += (unsigned long long)h.x;
-    atomicOr(reinterpret_cast<unsigned long long *>(&W.mask[(v >> 6) - sr]), 1ull << (v & 63));
-  }
+  if (found) bu_found<RowT>(W, v, h.x, hit, sr, level, dist, parent, C);
+  const uint64_t lm = __ballot(longrow);
+  if (lm) bu_long_rows(G, W, lm, v, h.x, front, sr, level, dist, parent, C);
   const uint64_t dm = __ballot(defer);
   if (defer) {
     const unsigned slot = (dh + dc + lanes_below(dm)) & (kDefer - 1);
@@ -1178,17 +1272,39 @@ template <class RowT>
 __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char *lds,
                                          unsigned long long (&counts)[kPartials]) {
   BuWaveLds &W = reinterpret_cast<BuWaveLds *>(lds)[threadIdx.x >> 6];
-  const uint32_t *front = reinterpret_cast<const uint32_t *>(c->bcur ? G.bm[1] : G.bm[0]);
-  uint64_t *next = c->bcur ? G.bm[0] : G.bm[1];
+  const int bcur = c->bcur;
+  uint64_t *next = bcur ? G.bm[0] : G.bm[1];
   const int32_t level = c->level;
   int32_t *dist = c->dist;
   int32_t *parent = c->parent;
+  const int64_t n_f = c->n_f;
   const int lane = lane_id();
   BuCount C;
   const int64_t wpb = blockDim.x >> 6;
   const int64_t nw = (int64_t)gridDim.x * wpb;
   const int64_t gw = xcd_block(gridDim.x) * wpb + (threadIdx.x >> 6);
-  const int64_t per = (G.words + nw - 1) / nw;
+  int64_t per = (G.words + nw - 1) / nw;
+  // With runs of whole summary bytes (8 << sshift words, which every grid of
+  // one search either has or has not), each wavefront writes the summary
+  // bytes of its own run: the next frontier's summary is then exact.
+  const int64_t sum_align = G.sshift >= 0 ? (int64_t)8 << G.sshift : 0;
+  const bool sums = G.sshift >= 0 && per >= sum_align;
+  if (sums) per = (per + sum_align - 1) / sum_align * sum_align;
+  // Small frontiers leave most summary bits clear: copy the summary into LDS
+  // and test it before each frontier word is read.  (Once most words hold a
+  // frontier vertex the copy would save little.)
+  Front front;
+  front.bits = reinterpret_cast<const uint32_t *>(bcur ? G.bm[1] : G.bm[0]);
+  front.lsum = nullptr;
+  front.sshift = G.sshift;
+  if (sums && n_f <= kSumFrontierWords * G.words) {
+    uint64_t *lsum = reinterpret_cast<uint64_t *>(lds + bu_lds_bytes(blockDim.x));
+    const uint64_t *fsm = bcur ? G.sm[1] : G.sm[0];
+    for (int i = threadIdx.x; i < G.swords; i += blockDim.x) lsum[i] = fsm[i];
+    front.lsum = lsum;
+  }
+  __syncthreads();
+  uint8_t *snext = sums ? reinterpret_cast<uint8_t *>(bcur ? G.sm[0] : G.sm[1]) : nullptr;
   const int64_t w_end = min(G.words, (gw + 1) * per);
   for (int64_t sr = gw * per; sr < w_end; sr += kWave) {
     const int nwd = (int)min((int64_t)kWave, w_end - sr);
@@ -1234,10 +1350,21 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
       pc = cnt;
     }
     // one coalesced store of the run's next-frontier and visited words
+    const uint64_t m = lane < nwd ? W.mask[lane] : 0ull;
     if (lane < nwd) {
-      const uint64_t m = W.mask[lane];
       next[sr + lane] = m;
       if (m) G.vis[sr + lane] = my_vis | m;
+    }
+    if (snext) {  // and the summary bytes of these words (sr is a multiple of 8 << sshift)
+      const uint64_t occ = __ballot(m != 0ull);
+      uint64_t sb = occ;
+      if (G.sshift > 0) {
+        const int g = 1 << G.sshift;
+        const bool any = lane < (kWave >> G.sshift) && ((occ >> (lane * g)) & ((1ull << g) - 1)) != 0ull;
+        sb = __ballot(any);
+      }
+      const int nbytes = (((nwd + (1 << G.sshift) - 1) >> G.sshift) + 7) >> 3;
+      if (lane < nbytes) snext[((sr >> G.sshift) >> 3) + lane] = (uint8_t)(sb >> (8 * lane));
     }
   }
   counts[0] = C.found;
@@ -1264,7 +1391,7 @@ __device__ __forceinline__ bool level_still(const Ctl *c, int32_t seen, int32_t 
 }
 
 template <class RowT, int D>
-__global__ void __launch_bounds__(1024, 8) k_level(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t mode,
+__global__ void __launch_bounds__(1024) k_level(DevG<RowT> G, int32_t nb_small, int32_t nb_med, int32_t mode,
                                                    int32_t lvl_mod, int32_t lvl_rem) {
   const Ctl *c = G.ctl;
   if (c->done) return;
@@ -1378,6 +1505,7 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.vis = g->vis;
   for (int s = 0; s < 2; ++s) {
     G.bm[s] = g->bm[s];
+    G.sm[s] = g->sm[s];
     G.qs[s] = g->qs[s];
     G.qm[s] = g->qm[s];
     G.ql[s] = g->ql[s];
@@ -1389,6 +1517,8 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.hrank = g->hrank;
   G.n = g->n;
   G.words = g->words;
+  G.sshift = g->sshift;
+  G.swords = (int32_t)g->swords;
   G.t1 = g->params.td_wave_degree;
   G.t2 = g->params.td_block_degree;
   G.tbu = g->params.bu_wave_degree;
@@ -1416,7 +1546,8 @@ Shapes shapes_of(const bfs_graph *g) {
   s.words_blocks = blocks_for(g->words, s.wpb, kMaxBlocks);
   s.bu_blocks = g->params.bu_blocks > 0 ? g->params.bu_blocks : s.words_blocks;
   s.lds = stage_bytes(s.bs);
-  s.level_lds = std::max(s.lds + (size_t)s.wpb * kCandTd * sizeof(int32_t), bu_lds_bytes(s.bs));
+  const size_t sum_lds = g->sshift >= 0 ? (size_t)g->swords * sizeof(uint64_t) : 0;
+  s.level_lds = std::max(s.lds + (size_t)s.wpb * kCandTd * sizeof(int32_t), bu_lds_bytes(s.bs) + sum_lds);
   return s;
 }
 
