@@ -163,11 +163,13 @@ class Graph:
             _check(load_library().bfs_destroy_graph(self.handle))
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # During interpreter shutdown the HIP runtime (and torch's use of it)
         # may already be torn down: a graph still open then is left to the
         # process exit instead of issuing frees, graph and stream destroys.
-        if sys.is_finalizing():
+        # (The check is bound at definition: module globals such as `sys`
+        # may already be cleared when this runs at shutdown.)
+        if _finalizing():
             return
         try:
             if self.handle and _lib is not None:
@@ -307,9 +309,9 @@ class Server:
     def __init__(self, handle):
         self.handle = handle
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # as Graph.__del__: nothing is issued once the interpreter is shutting down
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             if self.handle and _lib is not None:

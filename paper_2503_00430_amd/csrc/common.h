@@ -48,6 +48,7 @@ struct alignas(256) Ctl {
   int32_t levels_done;
   int32_t overflow; // nonzero: a level appended more entries than a queue holds
                     // (entries past the end were dropped; the search stops)
+  int32_t classless; // DevG::classless of this search
   int64_t n;        // vertex count
   int64_t n_f;      // size of the current frontier
   int64_t m_f;      // sum of degrees over the current frontier
@@ -116,6 +117,13 @@ struct DevG {
   uint32_t qcap, lcap;  // entries each small/medium queue and each large queue holds
   int32_t *slot;        // BFS_TD_DIST_PLAIN_CULL only (else null): per vertex, the
                         // queue position its last appender wrote
+  int32_t classless;    // top-down only, every degree <= t1: discoveries all go to the
+                        // small queue without reading their degree, and a level's
+                        // frontier degree sum m_f is added up when it is expanded
+  int32_t pers;         // nonzero inside the persistent kernel: data that workgroups of
+                        // one level hand to the next (queues, slots, plainly tested
+                        // distances) goes through the device-coherent level of the
+                        // memory system instead of an XCD's cache
 };
 
 // Scratch of the batched (multi-source) search, allocated on first use.

@@ -37,6 +37,23 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
   return (__attribute__((address_space(1))) T *)p;
 }
 
+// Loads and stores of data that workgroups hand to each other within one
+// kernel: with `coherent`, agent-scope atomic accesses, which are performed
+// at the device-wide coherence point (an XCD's L2 is not coherent with the
+// others'), so no cache write-back or invalidation is needed; otherwise plain
+// accesses (a kernel boundary orders them).
+template <class T>
+__device__ __forceinline__ T ld_x(const T *p, bool coherent) {
+  return coherent ? __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+template <class T>
+__device__ __forceinline__ void st_x(T *p, T v, bool coherent) {
+  if (coherent)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 // Workgroup order that gives each XCD a contiguous range of workgroups
 // (consecutive workgroup ids are dealt round-robin to the 8 XCDs).
 __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {

@@ -164,8 +164,8 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       if (slot < cap)
         (bb == kSmall ? S.small : S.medium)[slot] = v;
       else if (gbase + (slot - first_over) < G.qcap && gbase + (slot - first_over) >= gbase) {
-        global_queue(G, qn, bb)[gbase + (slot - first_over)] = v;
-        if (G.slot) G.slot[v] = (int32_t)(gbase + (slot - first_over));
+        st_x(global_queue(G, qn, bb) + gbase + (slot - first_over), v, G.pers);
+        if (G.slot) st_x(G.slot + v, (int32_t)(gbase + (slot - first_over)), G.pers);
       } else {
         flag_overflow(G.ctl);  // past the end: dropped, and the decide step stops the search
       }
@@ -185,7 +185,7 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       if (slot < cap)
         S.large[slot] = e;
       else if (gbase + (slot - first_over) < G.lcap && gbase + (slot - first_over) >= gbase)
-        gq[gbase + (slot - first_over)] = e;
+        st_x(gq + gbase + (slot - first_over), e, G.pers);
       else
         flag_overflow(G.ctl);
     }
@@ -226,16 +226,16 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   // grow, and the decide step turns that into an error)
   for (unsigned i = threadIdx.x; i < count[kSmall]; i += blockDim.x)
     if (gbase[kSmall] + i < G.qcap) {
-      qs[gbase[kSmall] + i] = S.small[i];
-      if (G.slot) G.slot[S.small[i]] = (int32_t)(gbase[kSmall] + i);
+      st_x(qs + gbase[kSmall] + i, S.small[i], G.pers);
+      if (G.slot) st_x(G.slot + S.small[i], (int32_t)(gbase[kSmall] + i), G.pers);
     }
   for (unsigned i = threadIdx.x; i < count[kMedium]; i += blockDim.x)
     if (gbase[kMedium] + i < G.qcap) {
-      qm[gbase[kMedium] + i] = S.medium[i];
-      if (G.slot) G.slot[S.medium[i]] = (int32_t)(gbase[kMedium] + i);
+      st_x(qm + gbase[kMedium] + i, S.medium[i], G.pers);
+      if (G.slot) st_x(G.slot + S.medium[i], (int32_t)(gbase[kMedium] + i), G.pers);
     }
   for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x)
-    if (gbase[kLarge] + i < G.lcap) ql[gbase[kLarge] + i] = S.large[i];
+    if (gbase[kLarge] + i < G.lcap) st_x(ql + gbase[kLarge] + i, S.large[i], G.pers);
   __syncthreads();
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -312,8 +312,10 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->qcap[1] = G.lcap;
     c->n = G.n;
     c->n_f = 1;
-    c->m_f = deg;
-    c->m_u = nnz - deg;
+    // (classless searches add a level's m_f up while expanding it)
+    c->classless = G.classless;
+    c->m_f = G.classless ? 0 : deg;
+    c->m_u = G.classless ? nnz : nnz - deg;
     c->sum_mf = 0;
     c->reached = 1;
     for (int q = 0; q < 2; ++q)
@@ -364,13 +366,18 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   // number moved on (see publish_level).
   if (bumped < 0) publish_level(c, L + 1);
   const int64_t found = (int64_t)tot[0];
-  const int64_t fdeg = (int64_t)tot[1];
+  // tot[1]: the degree sum of the vertices found, i.e. the next level's m_f;
+  // in a classless search, this level's own m_f (summed while expanding)
+  const bool classless = c->classless != 0;
+  const int64_t fdeg = classless ? 0 : (int64_t)tot[1];
+  const int64_t mf = classless ? (int64_t)tot[1] : c->m_f;
+  if (classless) c->m_u -= mf;
   if (L < c->rec_cap) {
     LevelRec r;
     r.level = L;
     r.dir = cur;
     r.n_f = c->n_f;
-    r.m_f = c->m_f;
+    r.m_f = mf;
     r.m_u = c->m_u;
     r.found = found;
     r.scanned = (int64_t)tot[2];
@@ -378,7 +385,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     recs[L] = r;
   }
   c->levels_done = L + 1;
-  c->sum_mf += c->m_f;
+  c->sum_mf += mf;
   c->reached += found;
   if (cur == kTD) {
     // the next frontier was appended to the other queue set; the old set
@@ -499,6 +506,23 @@ struct TdLevel {
   bool from_bitmap;    // the frontier is the bitmap of a bottom-up level
 };
 
+// The distance a top-down claim writes, and the distance read of the plain
+// visited test.  Distances are streamed out (nothing reads them back), except
+// that the plain test reads them: in the persistent kernel, where no kernel
+// boundary separates the levels, those go through the device-coherent level
+// (a store is complete before its workgroup arrives at the level's end).
+template <class RowT>
+__device__ __forceinline__ void dist_store(const DevG<RowT> &G, int32_t *p, int32_t d) {
+  if (G.pers && G.td_visited != BFS_TD_VISITED_BITMAP && G.td_visited != BFS_TD_DIST_CAS)
+    __hip_atomic_store(p, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    __builtin_nontemporal_store(d, gptr(p));
+}
+template <class RowT>
+__device__ __forceinline__ int32_t dist_test_load(const DevG<RowT> &G, const int32_t *p) {
+  return G.pers ? __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *gptr(p);
+}
+
 // Levels whose frontier has fewer edges than this claim with the atomic
 // alone: reading the visited word first saves the atomics on vertices
 // already visited, which only pays where there are many; on small levels
@@ -525,15 +549,15 @@ __device__ __forceinline__ void td_visit(const DevG<RowT> &G, const Stage &S, in
       }
     }
     else if (G.td_visited == BFS_TD_DIST_CAS) claimed = atomicCAS(dist + v, -1, level + 1) == -1;
-    else claimed = *gptr(dist + v) < 0;  // plain test: racing discoverers may all pass
+    else claimed = dist_test_load(G, dist + v) < 0;  // plain test: racing discoverers may all pass
   }
   if (claimed) {
     win = true;
     // (streaming stores, plain: every writer of v stores this same value)
-    __builtin_nontemporal_store(level + 1, gptr(dist + v));
+    dist_store(G, dist + v, level + 1);
     if (parent) __builtin_nontemporal_store(u, gptr(parent + v));
     fbm_set(T.fbm, T.fsm, T.sshift, v);
-    deg = G.head[v].x;
+    deg = G.classless ? 0 : G.head[v].x;
     nfound += 1;
     dfound += (unsigned long long)deg;
   }
@@ -571,11 +595,11 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
 }
 
 // Expands frontier vertex u of the calling lane (`act`; h = its head record,
-// row0 = its row offset) one lane per vertex: the head neighbours are
+// row0 = its row offset) one lane per vertex: the first four neighbours are
 // claimed together (their visited words, the claims and the new vertices'
 // degrees are three rounds of independent requests instead of three per
-// neighbour), then the rest of the row in lock-step with the wavefront.
-// All lanes of the wavefront call it together.
+// neighbour), then the rest of the row kTdUnroll neighbours at a time in
+// lock-step with the wavefront.  All lanes of the wavefront call it together.
 constexpr int kTdUnroll = 2;  // neighbours per lane per step in the wavefront / workgroup roles
 
 // Claims K neighbours x[k] (-1: none) of frontier vertex u[k] per lane
@@ -605,18 +629,18 @@ __device__ __forceinline__ void td_claim_batch(const DevG<RowT> &G, const Stage 
   } else {  // Section 2, BFS-NonAtomic (either form): a plain test, duplicates allowed
     int32_t d[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) d[k] = x[k] >= 0 ? *gptr(T.dist + x[k]) : 0;
+    for (int k = 0; k < K; ++k) d[k] = x[k] >= 0 ? dist_test_load(G, T.dist + x[k]) : 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) win[k] = x[k] >= 0 && d[k] < 0;
   }
-  int32_t dv[K];
+  int32_t dv[K];  // the new vertices' degrees (their queue class and the next m_f)
 #pragma unroll
-  for (int k = 0; k < K; ++k) dv[k] = win[k] ? G.head[x[k]].x : 0;
+  for (int k = 0; k < K; ++k) dv[k] = win[k] && !G.classless ? G.head[x[k]].x : 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if (win[k]) {
       // streaming stores, plain: every writer of x[k] stores this same value
-      __builtin_nontemporal_store(T.level + 1, gptr(T.dist + x[k]));
+      dist_store(G, T.dist + x[k], T.level + 1);
       if (T.parent) __builtin_nontemporal_store(u[k], gptr(T.parent + x[k]));
       fbm_set(T.fbm, T.fsm, T.sshift, x[k]);
       nfound += 1;
@@ -632,14 +656,21 @@ __device__ __forceinline__ void td_expand_lane(const DevG<RowT> &G, const Stage 
                                                unsigned long long &nfound, unsigned long long &dfound) {
   const int64_t deg = act ? h.x : 0;
   {
-    const int32_t x[3] = {act ? h.y : -1, act ? h.z : -1, act ? h.w : -1};
-    const int32_t uu[3] = {u, u, u};
-    td_claim_batch<3>(G, S, T, qn, x, uu, nfound, dfound);
+    // the three head neighbours and the row's fourth entry (read from the
+    // row while the head record is in hand) are claimed together, so rows of
+    // up to four take one round of claims (a lattice's rows)
+    const int32_t x[4] = {act ? h.y : -1, act ? h.z : -1, act ? h.w : -1, deg > 3 ? G.col[row0 + 3] : -1};
+    const int32_t uu[4] = {u, u, u, u};
+    td_claim_batch<4>(G, S, T, qn, x, uu, nfound, dfound);
   }
-  for (int64_t j = 3; __ballot(j < deg); ++j) {  // rest of the row; j is wave-uniform
-    const bool has = j < deg;
-    const int32_t v = has ? G.col[row0 + j] : 0;
-    td_visit(G, S, qn, T, has, u, v, T.m_f >= kPreloadMinEdges, nfound, dfound);
+  for (int64_t j = 4; __ballot(j < deg); j += kTdUnroll) {  // rest of the row; j is wave-uniform
+    int32_t x[kTdUnroll], uu[kTdUnroll];
+#pragma unroll
+    for (int q = 0; q < kTdUnroll; ++q) {
+      x[q] = j + q < deg ? G.col[row0 + j + q] : -1;
+      uu[q] = u;
+    }
+    td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
   }
 }
 
@@ -684,12 +715,13 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     for (int64_t round = (int64_t)blk * blockDim.x; round < cnt; round += step) {
       const int64_t i = round + wib * kWave + lane;
       bool act = i < cnt;
-      const int32_t u = act ? q[i] : 0;
-      if (act && G.slot) act = G.slot[u] == (int32_t)i;  // culled duplicate: expand only the recorded copy
+      const int32_t u = act ? ld_x(q + i, G.pers) : 0;
+      if (act && G.slot) act = ld_x(G.slot + u, G.pers) == (int32_t)i;  // culled duplicate: expand only the recorded copy
       int4 h = make_int4(0, -1, -1, -1);
       int64_t row0 = 0;
       if (act) {
         h = G.head[u];  // degree and first three neighbours
+        if (G.classless) dfound += (unsigned long long)h.x;  // this level's m_f
         row0 = (int64_t)G.rp[u];  // issued together with the head load
         fbm_clear(T.fbm, u);
       }
@@ -707,8 +739,8 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     for (int64_t round = (int64_t)(blk - nb_small) * wpb; round < items; round += waves) {
       const int64_t it = round + wib;
       const int64_t i = it / kpv, sub = it - i * kpv;
-      const int32_t u = it < items ? q[i] : -1;  // uniform within the wavefront
-      if (u >= 0 && (!G.slot || G.slot[u] == (int32_t)i)) {  // (culled duplicates skip)
+      const int32_t u = it < items ? ld_x(q + i, G.pers) : -1;  // uniform within the wavefront
+      if (u >= 0 && (!G.slot || ld_x(G.slot + u, G.pers) == (int32_t)i)) {  // (culled duplicates skip)
         if (lane == 0 && sub == 0) fbm_clear(T.fbm, u);
         const int64_t beg = (int64_t)G.rp[u], end = (int64_t)G.rp[u + 1];
         for (int64_t b = beg + sub * kWave * kTdUnroll; b < end; b += (int64_t)kWave * kTdUnroll * kpv) {
@@ -729,7 +761,7 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
     const uint64_t *q = qc ? G.ql[1] : G.ql[0];
     const int64_t nbl = (int64_t)nblk - nb_small - nb_med;
     for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
-      const uint64_t e = q[i];
+      const uint64_t e = ld_x(q + i, G.pers);
       const int32_t u = (int32_t)(uint32_t)e;
       const int64_t chunk = (int64_t)(e >> 32);
       if (chunk == 0 && threadIdx.x == 0) fbm_clear(T.fbm, u);
@@ -949,60 +981,169 @@ __device__ __forceinline__ void end_level(const DevG<RowT> &G, int32_t mode, con
 }
 
 // Persistent top-down search (top-down-only policies): every level of the
-// search in one cooperative launch.  Workgroups process a level, then meet
-// at a grid barrier; the last workgroup to arrive reduces the level's counts
-// and applies the decide step before releasing the others.  Cross-workgroup
-// data (queues, counts, control block) is ordered by agent-scope release
-// fences before arriving and acquire fences after leaving, and the level
-// state is read with device-scope atomic loads.
+// search in one cooperative launch, with no cache write-back or invalidation
+// between levels.  Data one level hands to the next crosses XCDs through
+// the device-coherent level of the memory system: queue entries (and culled
+// copies' slots and plainly tested distances) are written and read with
+// agent-scope accesses (G.pers), counts are added with atomics, and the
+// control block is read and written with agent-scope accesses.  The
+// distances and parents of the bitmap and compare-and-swap visited tests
+// are not read during the search.  A level ends like this:
+//   1. every thread waits for its own stores to complete; the workgroup adds
+//      its degree sum to an accumulator, waits for that, then adds
+//      (found << 11) + 1 to the arrival word with one returning atomic;
+//   2. the workgroup whose arrival completes the count (the word's low bits
+//      reach the grid size) takes the totals, clears both words, applies the
+//      decide step with agent-scope accesses, waits for them, and bumps the
+//      generation number; the others poll it (bounded: a wait that outlasts
+//      kPersistSpinLimit polls ends the search with an error flag).
+constexpr uint64_t kPersistSpinLimit = 1ull << 26;
+constexpr int kArrivalBits = 11;  // arrivals per level < 2^11 (at most kMaxBlocks workgroups)
+
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T ldc(const T &f) {
+  return __hip_atomic_load(const_cast<T *>(&f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void stc(T &f, T v) {
+  __hip_atomic_store(&f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The decide step of a top-down-only level inside the persistent kernel
+// (decide_apply's top-down branch, with device-coherent control-block
+// accesses).  Every field is loaded in one batch of independent loads and
+// every store issued in one batch, so the step costs two round trips to the
+// coherence point rather than one per field.  One thread.
+__device__ void decide_persistent(Ctl *c, LevelRec *recs, int64_t found, int64_t fdeg, unsigned qcap0,
+                                  unsigned qcap1, bool classless) {
+  const int32_t L = ldc(c->level);
+  const int32_t qcur = ldc(c->qcur);
+  const int32_t rec_cap = ldc(c->rec_cap);
+  const int32_t over = ldc(c->overflow);
+  const int64_t n_f = ldc(c->n_f), m_f = ldc(c->m_f), m_u = ldc(c->m_u);
+  const int64_t sum_mf = ldc(c->sum_mf), reached = ldc(c->reached);
+  unsigned q[2][3];
+  for (int s = 0; s < 2; ++s)
+    for (int b = 0; b < 3; ++b) q[s][b] = ldc(c->qcnt[s][b]);
+  // (classless: fdeg is this level's own m_f, summed while expanding it)
+  const int64_t mf = classless ? fdeg : m_f;
+  const int64_t mu = classless ? m_u - fdeg : m_u;
+  const int32_t nq = qcur ^ 1;  // the next frontier's queue set
+  const unsigned *qn = nq ? q[1] : q[0];
+  const bool overflow = over || qn[kSmall] > qcap0 || qn[kMedium] > qcap0 || qn[kLarge] > qcap1;
+  const bool end = overflow || found == 0;
+  if (L < rec_cap) {  // (read by the host after the kernel)
+    LevelRec r;
+    r.level = L;
+    r.dir = kTD;
+    r.n_f = n_f;
+    r.m_f = mf;
+    r.m_u = mu;
+    r.found = found;
+    r.scanned = 0;
+    r.examined = 0;
+    recs[L] = r;
+  }
+  stc(c->levels_done, L + 1);
+  stc(c->sum_mf, sum_mf + mf);
+  stc(c->reached, reached + found);
+  for (int b = 0; b < 3; ++b) stc(c->qcnt[qcur][b], 0u);  // emptied for the level after
+  stc(c->qcur, nq);
+  if (overflow) stc(c->overflow, 1);
+  if (end) {
+    stc(c->conv, (int32_t)kConvNone);
+    stc(c->done, 1);
+  } else {
+    stc(c->n_f, found);
+    stc(c->m_f, classless ? (int64_t)0 : fdeg);
+    stc(c->m_u, classless ? mu : m_u - fdeg);
+  }
+  stc(c->level, L + 1);
 }
 
 template <class RowT>
 __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb_small, int32_t nb_med) {
   extern __shared__ __align__(16) char lds[];
-  __shared__ int last;
+  __shared__ unsigned long long wsum[2][16];
+  __shared__ int go;
   Ctl *c = G.ctl;
+  unsigned long long *acc = G.partials + kAccOffset;             // degree sum of the level
+  unsigned long long *arrive = G.partials + kArriveOffset;       // (found << 11) + arrivals
+  uint32_t *gen = reinterpret_cast<uint32_t *>(G.partials + kArriveOffset + kLineU64);  // levels released
   for (int64_t it = 0; it <= G.n; ++it) {
-    if (__hip_atomic_load(&c->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;  // uniform
+    if (ldc(c->done)) break;  // uniform: read after the release every workgroup saw
     TdLevel T;
-    T.qcur = (int32_t)ld_agent(reinterpret_cast<const uint32_t *>(&c->qcur));
-    T.level = (int32_t)ld_agent(reinterpret_cast<const uint32_t *>(&c->level));
+    T.qcur = ldc(c->qcur);
+    T.level = ldc(c->level);
     for (int b = 0; b < 3; ++b) T.cnt[b] = ld_agent(&c->qcnt[T.qcur][b]);
+    T.m_f = ldc(c->m_f);
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
     T.fbm = nullptr;  // top-down only: no frontier bitmap to keep
     T.fsm = nullptr;
     T.sshift = G.sshift;
-    T.m_f = INT64_MAX;  // every workgroup takes part anyway: always split long medium rows
     T.from_bitmap = false;
     const Stage S = stage_open(lds);
     unsigned long long counts[2];
     td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med, counts);
-    block_partials<2>(G, counts);
-    // grid barrier; the last arrival decides.  Every wavefront releases its
-    // own stores (queue entries, partial counts) before the workgroup arrives.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&c->bar_count, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (last) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      unsigned long long tot[kPartials];
-      reduce_partials<true>(G.partials, gridDim.x, tot);
-      if (threadIdx.x == 0) {
-        decide_apply(c, G.recs, tot);
-        __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    } else if (threadIdx.x == 0) {
-      const uint32_t g0 = (uint32_t)it;  // generation number before this level's release
-      while (ld_agent(&c->bar_gen) == g0) __builtin_amdgcn_s_sleep(1);
+    // this workgroup's stores are complete before it arrives
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const int w = threadIdx.x >> 6;
+    const unsigned long long f = wave_sum(counts[0]), d = wave_sum(counts[1]);
+    if (lane_id() == 0) {
+      wsum[0][w] = f;
+      wsum[1][w] = d;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tf = 0, td = 0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        tf += wsum[0][i];
+        td += wsum[1][i];
+      }
+      if (td) atomicAdd(acc, td);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      const unsigned long long mine = (tf << kArrivalBits) + 1ull;
+      const unsigned long long old = atomicAdd(arrive, mine);
+      const unsigned long long now = old + mine;
+      int ended = 0;
+      if ((now & ((1ull << kArrivalBits) - 1)) == gridDim.x) {  // the last arrival: decide
+        const int64_t found = (int64_t)(now >> kArrivalBits);
+        const int64_t fdeg = (int64_t)atomicExch(acc, 0ull);
+        atomicExch(arrive, 0ull);
+        decide_persistent(c, G.recs, found, fdeg, G.qcap, G.lcap, G.classless != 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const uint32_t g0 = (uint32_t)it;  // releases so far
+        uint64_t spins = 0;
+        while (ld_agent(gen) == g0) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kPersistSpinLimit) {  // a workgroup that never arrives: stop everyone
+            stc(c->overflow, 2);
+            stc(c->done, 1);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ended = 1;
+            break;
+          }
+        }
+      }
+      go = !ended;
+    }
+    __syncthreads();
+    if (!go) break;
+  }
+  // the last decide publishes the final state for the host (one thread of
+  // the deciding workgroup, after invalidating its XCD's view)
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    // workgroup 0 waits until every level has been released (it left the
+    // loop after seeing done), then publishes
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    publish(c);
   }
 }
 
@@ -1526,6 +1667,8 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.qcap = (uint32_t)g->q_cap;
   G.lcap = (uint32_t)g->ql_cap;
   G.slot = g->params.td_visited == BFS_TD_DIST_PLAIN_CULL ? g->slot : nullptr;
+  G.pers = 0;
+  G.classless = (resolved_policy(g) == BFS_POLICY_TD_ONLY && g->max_degree <= G.t1) ? 1 : 0;
   return G;
 }
 
@@ -1841,7 +1984,9 @@ int persistent_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st) {
   const int nb_large = classes == 3 ? std::max(1, blocks / 4) : 0;
   const int nb_small = blocks - nb_med - nb_large;
   int32_t a_small = nb_small, a_med = nb_med;
-  void *args[] = {const_cast<DevG<RowT> *>(&G), &a_small, &a_med};
+  DevG<RowT> Gp = G;
+  Gp.pers = 1;  // levels hand their queues to each other inside the kernel
+  void *args[] = {&Gp, &a_small, &a_med};
   BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_td_persistent<RowT>), dim3(blocks),
                                      dim3(S.bs), args, S.lds, st));
   bool published = false;
@@ -1917,6 +2062,10 @@ int run_impl(bfs_graph *g, int32_t s, int32_t *dist, int32_t *parent) {
   L.host_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   L.loop = loop;
   L.policy = policy;
+  if (h.overflow == 2)
+    return fail(BFS_ERR_DEVICE, "the persistent search stopped at level %d: a workgroup waited more than "
+                                "%llu polls for the level to end", h.levels_done,
+                (unsigned long long)kPersistSpinLimit);
   if (h.overflow)
     return fail(BFS_ERR_OUT_OF_MEMORY,
                 "level %d appended more frontier entries than the queues hold (%lld per small/medium "
