@@ -290,7 +290,7 @@ def policy_study(bfs, torch, gh, sources, reps=2):
     dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
     out = {}
     for pol, name in POLICY_NAMES.items():
-        bfs.bfs_set_params(gh, policy=pol)
+        bfs.bfs_set_params(gh, policy=pol, loop=bfs.BFS_LOOP_GRAPH)
         bfs.bfs_run(gh, int(sources[0]), dist)
         per, sched = {}, {}
         for _ in range(reps):
@@ -325,7 +325,7 @@ def ablation(bfs, torch, gh, sources, reps=1):
     dist = torch.empty(gh.n, dtype=torch.int32, device="cuda")
     out, nf_base, per_level_base = {}, None, None
     for mode, name in TD_VISITED.items():
-        bfs.bfs_set_params(gh, policy=bfs.BFS_POLICY_TD_ONLY, td_visited=mode)
+        bfs.bfs_set_params(gh, policy=bfs.BFS_POLICY_TD_ONLY, td_visited=mode, loop=bfs.BFS_LOOP_GRAPH)
         per, nf, first_levels = {}, 0, None
         try:
             bfs.bfs_run(gh, int(sources[0]), dist)
@@ -362,10 +362,17 @@ def ablation(bfs, torch, gh, sources, reps=1):
     return out
 
 
+LOOP_NAMES = {0: "auto (captured hipGraph loop)", 1: "host loop", 2: "captured hipGraph loop",
+              3: "persistent top-down kernel", 4: "queued loop"}
+
+
 def bench_mesh(bfs, torch, reps=2, cpu=True):
-    """4096 x 4096 perturbed lattice, 16 sources (top-down only, captured loop)."""
+    """4096 x 4096 perturbed lattice, 16 sources (top-down only, with the
+    level loop its tuned parameters select), and the captured loop on 4 of
+    the sources beside it."""
     g, sources, _ = make_graph("grid4096")
     gh, _ = make_handle(bfs, g)
+    tuned_loop = bfs.bfs_get_params(gh)["loop"]
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
     bfs.bfs_run(gh, int(sources[0]), dist)  # warm-up (captures the level loop)
     per, outs = {}, {}
@@ -379,12 +386,25 @@ def bench_mesh(bfs, torch, reps=2, cpu=True):
             if rep == reps - 1:
                 outs[int(s)] = dist.cpu().numpy().astype("<i4")
     teps = [e / statistics.median(t) for e, t in per.values()]
+    captured = None
+    if tuned_loop not in (0, bfs.BFS_LOOP_GRAPH):
+        params = bfs.bfs_get_params(gh)
+        bfs.bfs_set_params(gh, loop=bfs.BFS_LOOP_GRAPH)
+        bfs.bfs_run(gh, int(sources[0]), dist)
+        ct = []
+        for s in sources[:4]:
+            bfs.bfs_run(gh, int(s), dist)
+            run, _ = bfs.bfs_get_run_stats(gh)
+            ct.append(run["edges"] / (run["host_ms"] / 1e3))
+        captured = round(len(ct) / sum(1.0 / t for t in ct) / 1e9, 4)
+        bfs.bfs_set_params(gh, **params)
     policies = policy_study(bfs, torch, gh, sources[:4], reps=1)
     visited = ablation(bfs, torch, gh, sources[:4])
     gh.close()
     hm = len(teps) / sum(1.0 / t for t in teps) / 1e9
     mean_ms = statistics.mean(statistics.median(t) for _, t in per.values()) * 1e3
     out = {"workload": "grid4096_p0.1_16src", "n": g.n, "nnz": g.nnz, "gteps_hm": round(hm, 4),
+           "loop": LOOP_NAMES.get(tuned_loop, tuned_loop), "captured_loop_gteps_hm_4src": captured,
            "ms_per_bfs": round(mean_ms, 3), "levels_mean": round(statistics.mean(levels), 1),
            "us_per_level": round(mean_ms * 1e3 / statistics.mean(levels), 2),
            "parity": parity("grid4096", outs),

@@ -40,6 +40,8 @@ SINGLE_SPACE = {
     "graph_td_blocks": [64, 128, 256, 512],
 }
 GRAPH_SPACE = {
+    # captured hipGraph chunks of level kernels, or one persistent launch
+    "loop": [L.BFS_LOOP_GRAPH, L.BFS_LOOP_PERSISTENT],
     "graph_td_blocks": [16, 32, 64, 128, 256],
     "graph_chunk_levels": [8, 32, 128],
     "block_size": [256, 512, 1024],

@@ -98,6 +98,8 @@ struct DevG {
   const int4 *head;     // per vertex: {degree, first three neighbours or -1}
   const int4 *headc;    // the same records for the non-isolated vertices only, in id order
   const uint32_t *hrank;  // per word: non-isolated vertices in the words before it
+  const uint32_t *rpc;  // row offsets of the non-isolated vertices in headc order (null
+                        // when nnz >= 2^32: then rp is read)
   uint64_t *vis;        // visited bitmap
   uint64_t *bm[2];      // frontier bitmaps (current / next alternate)
   uint64_t *sm[2];      // their occupancy summaries: bit i set if words [i << sshift,
@@ -149,6 +151,7 @@ struct bfs_graph {
   int4 *head = nullptr;  // {degree, first three neighbours or -1} per vertex
   int4 *headc = nullptr;  // head records of the non-isolated vertices only, in id order
   uint32_t *hrank = nullptr;  // per word: count of non-isolated vertices in earlier words
+  uint32_t *rpc = nullptr;  // row offsets in headc order (allocated when nnz < 2^32)
   uint64_t *vis = nullptr;
   uint64_t *bm[2] = {nullptr, nullptr};
   uint64_t *sm[2] = {nullptr, nullptr};  // occupancy summaries of bm (see DevG)

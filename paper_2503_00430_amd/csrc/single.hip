@@ -102,18 +102,25 @@ __device__ __forceinline__ int bucket_of(const DevG<RowT> &G, int64_t deg) {
 // full (at workgroup-uniform points) and at the end.  Slots past a buffer's
 // capacity go straight to the global queue.  Layout of the dynamic LDS:
 // counts[4] | small[8 * bs] | medium[2 * bs] | large[bs] (8-byte entries).
+// Large vertices are staged one entry each, {chunk count, vertex}; the
+// flush writes their t2-edge chunk entries (lpre: the inclusive prefix sums
+// of the staged chunk counts, built by the flush).  Capacities per thread of
+// the workgroup: 8 small, 4 medium, 1 large (a large-role step claims two
+// neighbours per thread, so with a flush after each step its medium
+// discoveries always fit).
 struct Stage {
   unsigned *cnt;
   int32_t *small;
   int32_t *medium;
   uint64_t *large;
+  unsigned *lpre;
   unsigned cap_small, cap_medium, cap_large;
   __device__ unsigned cap(int b) const {
     return b == kSmall ? cap_small : (b == kMedium ? cap_medium : cap_large);
   }
 };
 
-__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)48 * bs; }
+__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)60 * bs; }
 
 __device__ __forceinline__ Stage stage_open(char *lds) {
   const unsigned bs = blockDim.x;
@@ -121,9 +128,10 @@ __device__ __forceinline__ Stage stage_open(char *lds) {
   S.cnt = reinterpret_cast<unsigned *>(lds);
   S.small = reinterpret_cast<int32_t *>(lds + 16);
   S.medium = S.small + 8 * bs;
-  S.large = reinterpret_cast<uint64_t *>(S.medium + 2 * bs);
+  S.large = reinterpret_cast<uint64_t *>(S.medium + 4 * bs);
+  S.lpre = reinterpret_cast<unsigned *>(S.large + bs);
   S.cap_small = 8 * bs;
-  S.cap_medium = 2 * bs;
+  S.cap_medium = 4 * bs;
   S.cap_large = bs;
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -171,25 +179,70 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       }
     }
   }
-  if (b == kLarge) {  // rare: one entry per t2-edge chunk
-    const unsigned nch = (unsigned)((deg + G.t2 - 1) / G.t2);
-    const unsigned base = atomicAdd(&S.cnt[kLarge], nch);
-    const unsigned cap = S.cap_large;
-    const unsigned first_over = base > cap ? base : cap;
-    const unsigned over = base + nch > cap ? base + nch - first_over : 0;
-    const unsigned gbase = over ? atomicAdd(&G.ctl->qcnt[qn][kLarge], over) : 0;
-    uint64_t *gq = qn ? G.ql[1] : G.ql[0];
-    for (unsigned k = 0; k < nch; ++k) {
-      const unsigned slot = base + k;
-      const uint64_t e = ((uint64_t)k << 32) | (uint32_t)v;
-      if (slot < cap)
-        S.large[slot] = e;
-      else if (gbase + (slot - first_over) < G.lcap && gbase + (slot - first_over) >= gbase)
-        st_x(gq + gbase + (slot - first_over), e, G.pers);
-      else
-        flag_overflow(G.ctl);
+  // Large vertices (rare): one staged entry each, holding its chunk count;
+  // the workgroup's flush writes the chunk entries with the other entries
+  // (one queue reservation per workgroup).  Lanes past the buffer write
+  // their chunk entries at once: the wavefront reserves them together and
+  // writes each vertex's chunks 64 at a time.
+  const bool isl = b == kLarge;
+  const uint64_t lm = __ballot(isl);
+  if (lm) {
+    const int leader = __ffsll((unsigned long long)lm) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&S.cnt[kLarge], (unsigned)__popcll(lm));
+    base = __shfl(base, leader);
+    const unsigned nch = isl ? (unsigned)((deg + G.t2 - 1) / G.t2) : 0u;
+    const unsigned slot = base + lanes_below(lm);
+    if (isl && slot < S.cap_large) S.large[slot] = ((uint64_t)nch << 32) | (uint32_t)v;
+    const bool spill = isl && slot >= S.cap_large;
+    uint64_t om = __ballot(spill);
+    if (om) {
+      const unsigned sn = spill ? nch : 0u;
+      unsigned incl = sn;  // inclusive prefix sum of the spilled chunk counts over the lanes
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+      }
+      const unsigned off = incl - sn;
+      const unsigned tot = __shfl(incl, kWave - 1);
+      unsigned gbase = 0;
+      if (lane == 0) gbase = atomicAdd(&G.ctl->qcnt[qn][kLarge], tot);
+      gbase = __shfl(gbase, 0);
+      uint64_t *gq = qn ? G.ql[1] : G.ql[0];
+      while (om) {  // one spilled vertex at a time; its chunks a lane each
+        const int l = __builtin_ctzll(om);
+        om &= om - 1;
+        const unsigned n = __shfl(nch, l), o = __shfl(off, l);
+        const int32_t vl = __shfl(v, l);
+        for (unsigned k = (unsigned)lane; k < n; k += kWave) {
+          const uint64_t pos = (uint64_t)gbase + o + k;
+          if (pos < G.lcap)
+            st_x(gq + pos, ((uint64_t)k << 32) | (uint32_t)vl, G.pers);
+          else
+            flag_overflow(G.ctl);  // past the end: dropped, and the decide step stops the search
+        }
+      }
     }
   }
+}
+
+// Inclusive prefix sum of x over the threads of the workgroup (thread
+// order).  Every thread of the workgroup calls it.
+__device__ __forceinline__ unsigned block_incl_scan(unsigned x) {
+  __shared__ unsigned wtot[16];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned t = __shfl_up(x, o);
+    if (lane >= o) x += t;
+  }
+  if (lane == kWave - 1) wtot[w] = x;
+  __syncthreads();
+  unsigned before = 0;
+  for (int i = 0; i < w; ++i) before += wtot[i];
+  __syncthreads();  // (wtot is reused by the next call)
+  return x + before;
 }
 
 // Copies the staged entries to queue set `qn` and empties the buffers; with
@@ -198,7 +251,7 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
 template <class RowT>
 __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S, int qn,
                                             bool only_if_half_full = false) {
-  __shared__ unsigned gbase[3], count[3];
+  __shared__ unsigned gbase[3], count[3], lchunks;
   __syncthreads();
   const unsigned bs = blockDim.x;
   if (only_if_half_full) {
@@ -207,10 +260,19 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
     __syncthreads();
     if (skip) return;  // uniform: the same counts were read by every thread
   }
+  // the staged large vertices' chunk counts, summed: entry t is thread t's
+  // (at most bs staged), the inclusive prefix sums go to S.lpre
+  {
+    const unsigned nl = S.cnt[kLarge] < S.cap_large ? S.cnt[kLarge] : S.cap_large;
+    const unsigned c = threadIdx.x < nl ? (unsigned)(S.large[threadIdx.x] >> 32) : 0u;
+    const unsigned incl = block_incl_scan(c);
+    if (threadIdx.x < nl) S.lpre[threadIdx.x] = incl;
+    if (threadIdx.x == bs - 1) lchunks = incl;
+    __syncthreads();
+  }
   if (threadIdx.x < 3) {
     const unsigned b = threadIdx.x;
-    const unsigned cap = b == kSmall ? 8 * bs : (b == kMedium ? 2 * bs : bs);  // as in stage_open
-    const unsigned n = S.cnt[b] < cap ? S.cnt[b] : cap;
+    const unsigned n = b == kLarge ? lchunks : (S.cnt[b] < S.cap(b) ? S.cnt[b] : S.cap(b));
     count[b] = n;
     gbase[b] = n ? atomicAdd(&G.ctl->qcnt[qn][b], n) : 0;
     // a range past the queue's end (or past 2^32 appends) loses entries: the
@@ -234,8 +296,20 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
       st_x(qm + gbase[kMedium] + i, S.medium[i], G.pers);
       if (G.slot) st_x(G.slot + S.medium[i], (int32_t)(gbase[kMedium] + i), G.pers);
     }
-  for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x)
-    if (gbase[kLarge] + i < G.lcap) st_x(ql + gbase[kLarge] + i, S.large[i], G.pers);
+  if (count[kLarge]) {  // chunk c of the staged run belongs to the first vertex whose prefix exceeds it
+    const unsigned nl = S.cnt[kLarge] < S.cap_large ? S.cnt[kLarge] : S.cap_large;
+    for (unsigned c = threadIdx.x; c < count[kLarge]; c += blockDim.x) {
+      unsigned lo = 0, hi = nl - 1;
+      while (lo < hi) {
+        const unsigned mid = (lo + hi) >> 1;
+        if (S.lpre[mid] > c) hi = mid;
+        else lo = mid + 1;
+      }
+      const unsigned first = lo ? S.lpre[lo - 1] : 0u;
+      if (gbase[kLarge] + c < G.lcap)
+        st_x(ql + gbase[kLarge] + c, ((uint64_t)(c - first) << 32) | (uint32_t)S.large[lo], G.pers);
+    }
+  }
   __syncthreads();
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -768,8 +842,14 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       const int64_t row_end = (int64_t)G.rp[u + 1];
       const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
       const int64_t end = min(row_end, beg + (int64_t)G.t2);
-      // kTdUnroll neighbours per lane per step, each step's ids coalesced
-      for (int64_t b = beg + wib * kWave * kTdUnroll; b < end; b += (int64_t)blockDim.x * kTdUnroll) {
+      // kTdUnroll neighbours per lane per step, each step's ids coalesced;
+      // the steps are workgroup-uniform, and the staging buffers are emptied
+      // after each one (a hub's neighbours are
+      // themselves of high degree: without that, their entries would
+      // overflow to the global queue with one contended atomic per
+      // wavefront, serialised at the counter)
+      for (int64_t step = beg; step < end; step += (int64_t)blockDim.x * kTdUnroll) {
+        const int64_t b = step + wib * kWave * kTdUnroll;
         int32_t x[kTdUnroll], uu[kTdUnroll];
 #pragma unroll
         for (int q = 0; q < kTdUnroll; ++q) {
@@ -778,8 +858,8 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
           uu[q] = u;
         }
         td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
+        stage_flush(G, S, qn);
       }
-      stage_flush(G, S, qn, true);
     }
   }
   stage_flush(G, S, qn);
@@ -1179,6 +1259,7 @@ struct BuWaveLds {
   uint32_t rank[kWave];  // and compacted-record offsets, one per word
   int32_t dv[kDefer];
   int32_t ddeg[kDefer];
+  int32_t dcr[kDefer];   // the deferred vertex's index in the compacted records
   uint64_t mask[kWave];
 };
 
@@ -1254,7 +1335,7 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
   if (act) {
     v = W.dv[slot];
     deg = W.ddeg[slot];
-    from = (int64_t)G.rp[v] + 3;
+    from = (G.rpc ? (int64_t)G.rpc[W.dcr[slot]] : (int64_t)G.rp[v]) + 3;
   }
   const int32_t len = act ? deg - 3 : 0;  // >= 1: deferred rows are longer than the head
   int32_t incl = len;  // inclusive prefix sum of the lengths over the lanes
@@ -1361,7 +1442,7 @@ __device__ __forceinline__ void bu_long_rows(const DevG<RowT> &G, BuWaveLds &W, 
 // 64 deferred rows when that many wait, and every deferred row after the
 // `last` batch of a run).
 template <class RowT>
-__device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, int32_t v, const int4 h, int cnt,
+__device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, int32_t v, int32_t cr, const int4 h, int cnt,
                                            const Front &front, int64_t sr, int32_t level, int32_t *dist,
                                            int32_t *parent, unsigned &dh, unsigned &dc, bool last, BuCount &C) {
   const int lane = lane_id();
@@ -1399,6 +1480,7 @@ __device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, in
     const unsigned slot = (dh + dc + lanes_below(dm)) & (kDefer - 1);
     W.dv[slot] = v;
     W.ddeg[slot] = h.x;
+    W.dcr[slot] = cr;
   }
   dc += (unsigned)__popcll(dm);
   while (dc >= kWave || (last && dc > 0)) {  // uniform; the last batch may leave up to 127
@@ -1457,7 +1539,7 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
     unsigned ch = 0, ct = 0;                   // candidate ring head / tail (uniform)
     unsigned dh = 0, dc = 0;                   // deferred ring head / count
     int pc = 0;                                // candidates of the batch in flight
-    int32_t pv = 0;
+    int32_t pv = 0, pcr = 0;
     int4 ph = make_int4(0, 0, -1, -1);
     for (;;) {
       if (act) {
@@ -1478,15 +1560,17 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
       // (an empty next batch marks the run's last resolve)
       const int cnt = (int)min(ct - ch, (unsigned)kWave);
       if (cnt == 0 && pc == 0) break;
-      int32_t bv = 0;
+      int32_t bv = 0, bcr = 0;
       int4 bh = make_int4(0, 0, -1, -1);
       if (lane < cnt) {
         bv = W.cand[(ch + lane) & (kCand - 1)];
-        bh = G.headc[W.crank[(ch + lane) & (kCand - 1)]];
+        bcr = W.crank[(ch + lane) & (kCand - 1)];
+        bh = G.headc[bcr];
       }
       ch += cnt;
-      if (pc) bu_resolve(G, W, pv, ph, pc, front, sr, level, dist, parent, dh, dc, cnt == 0, C);
+      if (pc) bu_resolve(G, W, pv, pcr, ph, pc, front, sr, level, dist, parent, dh, dc, cnt == 0, C);
       pv = bv;
+      pcr = bcr;
       ph = bh;
       pc = cnt;
     }
@@ -1612,10 +1696,13 @@ __global__ void k_build_head(const RowT *rp, const int32_t *col, int4 *head, int
 
 // Compacted head records: the record of the r-th non-isolated vertex (in
 // id order) at index r, so a bottom-up level whose candidates are dense
-// among the non-isolated vertices reads whole lines of records it uses.
-// One thread per 64-vertex word.
-__global__ void k_build_headc(const int4 *head, const uint64_t *iso, const uint32_t *hrank, int4 *headc,
-                              int64_t words) {
+// among the non-isolated vertices reads whole lines of records it uses; and,
+// when rpc is not null, the vertex's row offset at the same index (a
+// bottom-up level's deferred rows come from consecutive candidates, so their
+// offsets share lines).  One thread per 64-vertex word.
+template <class RowT>
+__global__ void k_build_headc(const int4 *head, const uint64_t *iso, const uint32_t *hrank, const RowT *rp,
+                              int4 *headc, uint32_t *rpc, int64_t words) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
     uint64_t live = ~iso[w];
@@ -1623,7 +1710,9 @@ __global__ void k_build_headc(const int4 *head, const uint64_t *iso, const uint3
     while (live) {
       const int b = __builtin_ctzll(live);
       live &= live - 1;
-      headc[r++] = head[w * kWave + b];
+      headc[r] = head[w * kWave + b];
+      if (rpc) rpc[r] = (uint32_t)rp[w * kWave + b];
+      ++r;
     }
   }
 }
@@ -1656,6 +1745,7 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.partials = g->partials;
   G.headc = g->headc;
   G.hrank = g->hrank;
+  G.rpc = g->rpc;
   G.n = g->n;
   G.words = g->words;
   G.sshift = g->sshift;
@@ -2085,8 +2175,12 @@ int build_head(bfs_graph *g) {
   else
     hipLaunchKernelGGL(k_build_head<int32_t>, dim3(blocks), dim3(bs), 0, nullptr,
                        static_cast<const int32_t *>(g->rp), g->col, g->head, g->n);
-  hipLaunchKernelGGL(k_build_headc, dim3(blocks), dim3(bs), 0, nullptr, g->head, g->iso, g->hrank, g->headc,
-                     g->words);
+  if (g->rp64)
+    hipLaunchKernelGGL(k_build_headc<int64_t>, dim3(blocks), dim3(bs), 0, nullptr, g->head, g->iso, g->hrank,
+                       static_cast<const int64_t *>(g->rp), g->headc, g->rpc, g->words);
+  else
+    hipLaunchKernelGGL(k_build_headc<int32_t>, dim3(blocks), dim3(bs), 0, nullptr, g->head, g->iso, g->hrank,
+                       static_cast<const int32_t *>(g->rp), g->headc, g->rpc, g->words);
   BFS_HIP(hipGetLastError());
   BFS_HIP(hipDeviceSynchronize());
   return BFS_OK;
