@@ -612,6 +612,9 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, mesh and serving sections")
+    ap.add_argument("--levels-json", default=None,
+                    help="write the instrumented pass's per-level records of every search to this file "
+                         "(the last --steps passes over the sources, in launch order)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched section (RMAT-22, 64 sources), e.g. to profile its kernel")
     args = ap.parse_args()
@@ -701,6 +704,9 @@ def main():
         step(inst)
     torch.cuda.synchronize()
     gteps_host_loop = hm_gteps(inst, "host_ms")
+    if args.levels_json:
+        with open(args.levels_json, "w") as f:
+            json.dump([{"source": s, "run": run, "levels": lvs} for s, run, lvs in inst], f)
     bfs.bfs_set_params(gh, **params)
     policies = None if args.no_extras else policy_study(bfs, torch, gh, sources[:16])
 

@@ -55,7 +55,8 @@ struct alignas(256) Ctl {
   int64_t m_u;      // sum of degrees over vertices not yet visited
   int64_t sum_mf;   // sum of m_f over all levels so far (= 2 * TEPS edge count)
   int64_t reached;  // vertices visited so far
-  unsigned int qcnt[2][3];  // entries held by queue set s, bucket b
+  unsigned int qcnt[2][3];  // entries held by queue set s, bucket b (large: one per vertex)
+  unsigned int qchunk[2];   // td_block_degree-edge chunks of the large vertices of set s
   unsigned int qcap[2];     // capacity of each small/medium queue, of each large queue
   int32_t *dist;    // outputs of the current search
   int32_t *parent;

@@ -102,25 +102,29 @@ __device__ __forceinline__ int bucket_of(const DevG<RowT> &G, int64_t deg) {
 // full (at workgroup-uniform points) and at the end.  Slots past a buffer's
 // capacity go straight to the global queue.  Layout of the dynamic LDS:
 // counts[4] | small[8 * bs] | medium[2 * bs] | large[bs] (8-byte entries).
-// Large vertices are staged one entry each, {chunk count, vertex}; the
-// flush writes their t2-edge chunk entries (lpre: the inclusive prefix sums
-// of the staged chunk counts, built by the flush).  Capacities per thread of
-// the workgroup: 8 small, 4 medium, 1 large (a large-role step claims two
-// neighbours per thread, so with a flush after each step its medium
-// discoveries always fit).
+// Large vertices are queued one entry each, {chunk count, vertex}, and the
+// queue set's chunk total is kept beside its counts: the top-down level that
+// expands them maps its chunk indices onto the entries (wv / wp: one window
+// of entries and the inclusive prefix sums of their chunk counts).  A hub's
+// chunks are thus never written out when the next level runs bottom-up.
+// Capacities per thread of the workgroup: 8 small, 4 medium, 2 large (a
+// large-role step claims two neighbours per thread, so with a flush after
+// each step its medium and large discoveries always fit: a hub-first row's
+// first chunk finds mostly hubs).
 struct Stage {
   unsigned *cnt;
   int32_t *small;
   int32_t *medium;
   uint64_t *large;
-  unsigned *lpre;
+  uint64_t *wv;
+  unsigned *wp;
   unsigned cap_small, cap_medium, cap_large;
   __device__ unsigned cap(int b) const {
     return b == kSmall ? cap_small : (b == kMedium ? cap_medium : cap_large);
   }
 };
 
-__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)60 * bs; }
+__host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)76 * bs; }
 
 __device__ __forceinline__ Stage stage_open(char *lds) {
   const unsigned bs = blockDim.x;
@@ -129,10 +133,11 @@ __device__ __forceinline__ Stage stage_open(char *lds) {
   S.small = reinterpret_cast<int32_t *>(lds + 16);
   S.medium = S.small + 8 * bs;
   S.large = reinterpret_cast<uint64_t *>(S.medium + 4 * bs);
-  S.lpre = reinterpret_cast<unsigned *>(S.large + bs);
+  S.wv = S.large + 2 * bs;
+  S.wp = reinterpret_cast<unsigned *>(S.wv + bs);
   S.cap_small = 8 * bs;
   S.cap_medium = 4 * bs;
-  S.cap_large = bs;
+  S.cap_large = 2 * bs;
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
   return S;
@@ -179,11 +184,9 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
       }
     }
   }
-  // Large vertices (rare): one staged entry each, holding its chunk count;
-  // the workgroup's flush writes the chunk entries with the other entries
-  // (one queue reservation per workgroup).  Lanes past the buffer write
-  // their chunk entries at once: the wavefront reserves them together and
-  // writes each vertex's chunks 64 at a time.
+  // Large vertices (rare): one staged entry each, {chunk count, vertex}.
+  // Lanes past the buffer append theirs at once (one reservation for the
+  // wavefront's spilled entries, and their chunks added to the set's total).
   const bool isl = b == kLarge;
   const uint64_t lm = __ballot(isl);
   if (lm) {
@@ -192,36 +195,26 @@ __device__ __forceinline__ void wave_stage(const DevG<RowT> &G, const Stage &S, 
     if (lane == leader) base = atomicAdd(&S.cnt[kLarge], (unsigned)__popcll(lm));
     base = __shfl(base, leader);
     const unsigned nch = isl ? (unsigned)((deg + G.t2 - 1) / G.t2) : 0u;
+    const uint64_t ent = ((uint64_t)nch << 32) | (uint32_t)v;
     const unsigned slot = base + lanes_below(lm);
-    if (isl && slot < S.cap_large) S.large[slot] = ((uint64_t)nch << 32) | (uint32_t)v;
+    if (isl && slot < S.cap_large) S.large[slot] = ent;
     const bool spill = isl && slot >= S.cap_large;
-    uint64_t om = __ballot(spill);
+    const uint64_t om = __ballot(spill);
     if (om) {
-      const unsigned sn = spill ? nch : 0u;
-      unsigned incl = sn;  // inclusive prefix sum of the spilled chunk counts over the lanes
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const unsigned t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-      }
-      const unsigned off = incl - sn;
-      const unsigned tot = __shfl(incl, kWave - 1);
+      const int sl = __ffsll((unsigned long long)om) - 1;
+      const unsigned long long chunks = wave_sum(spill ? (unsigned long long)nch : 0ull);
       unsigned gbase = 0;
-      if (lane == 0) gbase = atomicAdd(&G.ctl->qcnt[qn][kLarge], tot);
-      gbase = __shfl(gbase, 0);
-      uint64_t *gq = qn ? G.ql[1] : G.ql[0];
-      while (om) {  // one spilled vertex at a time; its chunks a lane each
-        const int l = __builtin_ctzll(om);
-        om &= om - 1;
-        const unsigned n = __shfl(nch, l), o = __shfl(off, l);
-        const int32_t vl = __shfl(v, l);
-        for (unsigned k = (unsigned)lane; k < n; k += kWave) {
-          const uint64_t pos = (uint64_t)gbase + o + k;
-          if (pos < G.lcap)
-            st_x(gq + pos, ((uint64_t)k << 32) | (uint32_t)vl, G.pers);
-          else
-            flag_overflow(G.ctl);  // past the end: dropped, and the decide step stops the search
-        }
+      if (lane == sl) {
+        gbase = atomicAdd(&G.ctl->qcnt[qn][kLarge], (unsigned)__popcll(om));
+        atomicAdd(&G.ctl->qchunk[qn], (unsigned)chunks);
+      }
+      gbase = __shfl(gbase, sl);
+      if (spill) {
+        const uint64_t pos = (uint64_t)gbase + lanes_below(om);
+        if (pos < G.lcap)
+          st_x((qn ? G.ql[1] : G.ql[0]) + pos, ent, G.pers);
+        else
+          flag_overflow(G.ctl);  // past the end: dropped, and the decide step stops the search
       }
     }
   }
@@ -255,26 +248,28 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
   __syncthreads();
   const unsigned bs = blockDim.x;
   if (only_if_half_full) {
-    const bool skip = S.cnt[kSmall] < 4 * bs && S.cnt[kMedium] < bs && S.cnt[kLarge] < bs / 2;
+    const bool skip = S.cnt[kSmall] < 4 * bs && S.cnt[kMedium] < 2 * bs && S.cnt[kLarge] < bs;
     // every thread has read the counts before any wavefront can stage again
     __syncthreads();
     if (skip) return;  // uniform: the same counts were read by every thread
   }
-  // the staged large vertices' chunk counts, summed: entry t is thread t's
-  // (at most bs staged), the inclusive prefix sums go to S.lpre
+  // the staged large vertices' chunks, summed (entries 2t and 2t + 1 are
+  // thread t's: at most 2 bs staged)
   {
     const unsigned nl = S.cnt[kLarge] < S.cap_large ? S.cnt[kLarge] : S.cap_large;
-    const unsigned c = threadIdx.x < nl ? (unsigned)(S.large[threadIdx.x] >> 32) : 0u;
-    const unsigned incl = block_incl_scan(c);
-    if (threadIdx.x < nl) S.lpre[threadIdx.x] = incl;
+    const unsigned i0 = 2 * threadIdx.x, i1 = i0 + 1;
+    const unsigned c0 = i0 < nl ? (unsigned)(S.large[i0] >> 32) : 0u;
+    const unsigned c1 = i1 < nl ? (unsigned)(S.large[i1] >> 32) : 0u;
+    const unsigned incl = block_incl_scan(c0 + c1);
     if (threadIdx.x == bs - 1) lchunks = incl;
     __syncthreads();
   }
   if (threadIdx.x < 3) {
     const unsigned b = threadIdx.x;
-    const unsigned n = b == kLarge ? lchunks : (S.cnt[b] < S.cap(b) ? S.cnt[b] : S.cap(b));
+    const unsigned n = S.cnt[b] < S.cap(b) ? S.cnt[b] : S.cap(b);
     count[b] = n;
     gbase[b] = n ? atomicAdd(&G.ctl->qcnt[qn][b], n) : 0;
+    if (b == kLarge && n) atomicAdd(&G.ctl->qchunk[qn], lchunks);
     // a range past the queue's end (or past 2^32 appends) loses entries: the
     // search stops at this level's decide step
     const uint64_t qend = (uint64_t)gbase[b] + n;
@@ -296,20 +291,8 @@ __device__ __forceinline__ void stage_flush(const DevG<RowT> &G, const Stage &S,
       st_x(qm + gbase[kMedium] + i, S.medium[i], G.pers);
       if (G.slot) st_x(G.slot + S.medium[i], (int32_t)(gbase[kMedium] + i), G.pers);
     }
-  if (count[kLarge]) {  // chunk c of the staged run belongs to the first vertex whose prefix exceeds it
-    const unsigned nl = S.cnt[kLarge] < S.cap_large ? S.cnt[kLarge] : S.cap_large;
-    for (unsigned c = threadIdx.x; c < count[kLarge]; c += blockDim.x) {
-      unsigned lo = 0, hi = nl - 1;
-      while (lo < hi) {
-        const unsigned mid = (lo + hi) >> 1;
-        if (S.lpre[mid] > c) hi = mid;
-        else lo = mid + 1;
-      }
-      const unsigned first = lo ? S.lpre[lo - 1] : 0u;
-      if (gbase[kLarge] + c < G.lcap)
-        st_x(ql + gbase[kLarge] + c, ((uint64_t)(c - first) << 32) | (uint32_t)S.large[lo], G.pers);
-    }
-  }
+  for (unsigned i = threadIdx.x; i < count[kLarge]; i += blockDim.x)
+    if (gbase[kLarge] + i < G.lcap) st_x(ql + gbase[kLarge] + i, S.large[i], G.pers);
   __syncthreads();
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -392,13 +375,16 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->m_u = G.classless ? nnz : nnz - deg;
     c->sum_mf = 0;
     c->reached = 1;
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 2; ++q) {
       for (int b = 0; b < 3; ++b) c->qcnt[q][b] = 0;
+      c->qchunk[q] = 0;
+    }
     const int b = bucket_of(G, deg);
     if (b == kLarge) {
       const unsigned nch = (unsigned)((deg + G.t2 - 1) / G.t2);
-      for (unsigned k = 0; k < nch; ++k) G.ql[0][k] = ((uint64_t)k << 32) | (uint32_t)s;
-      c->qcnt[0][kLarge] = nch;
+      G.ql[0][0] = ((uint64_t)nch << 32) | (uint32_t)s;
+      c->qcnt[0][kLarge] = 1;
+      c->qchunk[0] = nch;
     } else {
       (b == kSmall ? G.qs[0] : G.qm[0])[0] = s;
       if (G.slot) G.slot[s] = 0;
@@ -465,6 +451,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     // the next frontier was appended to the other queue set; the old set
     // becomes the target of the following top-down level
     for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
+    c->qchunk[c->qcur] = 0;
     c->qcur ^= 1;
     // with the visited test of plain loads and stores a vertex can be
     // appended once per racing discoverer; a set that outgrew its queues
@@ -501,8 +488,10 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
   // (top-down levels keep the frontier bitmap of hybrid searches current, so
   // only a switch back to top-down changes how the frontier is read)
   c->conv = (cur == kBU && nxt == kTD) ? kConvB2Q : kConvNone;
-  if (c->conv == kConvB2Q)
+  if (c->conv == kConvB2Q) {
     for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
+    c->qchunk[c->qcur] = 0;
+  }
   c->n_f = found;
   c->m_f = fdeg;
   c->m_u = m_u;
@@ -571,7 +560,8 @@ __device__ __forceinline__ void fbm_clear(uint64_t *fbm, int32_t u) {
 // Level state a top-down level needs, read once per level.
 struct TdLevel {
   int32_t qcur, level;
-  int64_t cnt[3];
+  int64_t cnt[3];      // queue entries per class (large: one per vertex)
+  int64_t nchunk;      // td_block_degree-edge chunks of the large vertices
   int64_t m_f;         // degree sum of the frontier (steers the medium-row split)
   int32_t *dist, *parent;
   uint64_t *fbm;       // current frontier bitmap (hybrid searches), else null
@@ -658,6 +648,8 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
   for (int s = 0; s < 2; ++s)
     for (int b = 0; b < 3; ++b) q[s][b] = c->qcnt[s][b];
   for (int b = 0; b < 3; ++b) t.cnt[b] = t.qcur ? q[1][b] : q[0][b];
+  const unsigned ch0 = c->qchunk[0], ch1 = c->qchunk[1];
+  t.nchunk = t.qcur ? ch1 : ch0;
   t.m_f = c->m_f;
   t.dist = c->dist;
   t.parent = c->parent;
@@ -831,35 +823,64 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       stage_flush(G, S, qn, true);
     }
   } else {
-    const int64_t cnt = T.cnt[kLarge];
+    // Large vertices: the queue holds one entry per vertex, {chunk count,
+    // vertex}; this role's workgroups take the chunks round-robin by index
+    // over the entries in queue order.  Every workgroup reads the entries a
+    // window at a time, with the prefix sums of their chunk counts, and
+    // finds the vertex of each of its chunks there.
+    const int64_t nlv = T.cnt[kLarge];
     const uint64_t *q = qc ? G.ql[1] : G.ql[0];
     const int64_t nbl = (int64_t)nblk - nb_small - nb_med;
-    for (int64_t i = blk - nb_small - nb_med; i < cnt; i += nbl) {
-      const uint64_t e = ld_x(q + i, G.pers);
-      const int32_t u = (int32_t)(uint32_t)e;
-      const int64_t chunk = (int64_t)(e >> 32);
-      if (chunk == 0 && threadIdx.x == 0) fbm_clear(T.fbm, u);
-      const int64_t row_end = (int64_t)G.rp[u + 1];
-      const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
-      const int64_t end = min(row_end, beg + (int64_t)G.t2);
-      // kTdUnroll neighbours per lane per step, each step's ids coalesced;
-      // the steps are workgroup-uniform, and the staging buffers are emptied
-      // after each one (a hub's neighbours are
-      // themselves of high degree: without that, their entries would
-      // overflow to the global queue with one contended atomic per
-      // wavefront, serialised at the counter)
-      for (int64_t step = beg; step < end; step += (int64_t)blockDim.x * kTdUnroll) {
-        const int64_t b = step + wib * kWave * kTdUnroll;
-        int32_t x[kTdUnroll], uu[kTdUnroll];
-#pragma unroll
-        for (int q = 0; q < kTdUnroll; ++q) {
-          const int64_t j = b + q * kWave + lane;
-          x[q] = j < end ? G.col[j] : -1;
-          uu[q] = u;
+    const int64_t r = blk - nb_small - nb_med;
+    __shared__ unsigned wtot;
+    int64_t cbase = 0;  // chunk index of the window's first chunk
+    // (the first chunk of this workgroup at or after cbase is
+    // cbase + (r - cbase) mod nbl; past the total, the workgroup is done)
+    for (int64_t w0 = 0; w0 < nlv && cbase + ((r - cbase % nbl) + nbl) % nbl < T.nchunk;
+         w0 += blockDim.x) {  // workgroup-uniform
+      const int64_t e = w0 + threadIdx.x;
+      const uint64_t ent = e < nlv ? ld_x(q + e, G.pers) : 0ull;
+      const unsigned incl = block_incl_scan((unsigned)(ent >> 32));
+      S.wv[threadIdx.x] = ent;
+      S.wp[threadIdx.x] = incl;
+      if (threadIdx.x == blockDim.x - 1) wtot = incl;
+      __syncthreads();
+      const int64_t tot = wtot;
+      const unsigned nent = (unsigned)min((int64_t)blockDim.x, nlv - w0);
+      for (int64_t j = cbase + ((r - cbase % nbl) + nbl) % nbl; j < cbase + tot; j += nbl) {
+        const unsigned jj = (unsigned)(j - cbase);  // (the same search in every thread)
+        unsigned lo = 0, hi = nent - 1;
+        while (lo < hi) {
+          const unsigned mid = (lo + hi) >> 1;
+          if (S.wp[mid] > jj) hi = mid;
+          else lo = mid + 1;
         }
-        td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
-        stage_flush(G, S, qn);
+        const int32_t u = (int32_t)(uint32_t)S.wv[lo];
+        const int64_t chunk = (int64_t)jj - (lo ? (int64_t)S.wp[lo - 1] : 0);
+        if (chunk == 0 && threadIdx.x == 0) fbm_clear(T.fbm, u);
+        const int64_t row_end = (int64_t)G.rp[u + 1];
+        const int64_t beg = (int64_t)G.rp[u] + chunk * G.t2;
+        const int64_t end = min(row_end, beg + (int64_t)G.t2);
+        // kTdUnroll neighbours per lane per step, each step's ids coalesced;
+        // the steps are workgroup-uniform, and the staging buffers are
+        // emptied after each one (a hub's neighbours are themselves of high
+        // degree: without that, their entries would overflow to the global
+        // queue with one contended atomic per wavefront)
+        for (int64_t step = beg; step < end; step += (int64_t)blockDim.x * kTdUnroll) {
+          const int64_t bb = step + wib * kWave * kTdUnroll;
+          int32_t x[kTdUnroll], uu[kTdUnroll];
+#pragma unroll
+          for (int qq = 0; qq < kTdUnroll; ++qq) {
+            const int64_t jn = bb + qq * kWave + lane;
+            x[qq] = jn < end ? G.col[jn] : -1;
+            uu[qq] = u;
+          }
+          td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
+          stage_flush(G, S, qn);
+        }
       }
+      cbase += tot;
+      __syncthreads();  // every thread is done with the window before the next one
     }
   }
   stage_flush(G, S, qn);
@@ -1131,6 +1152,7 @@ __device__ void decide_persistent(Ctl *c, LevelRec *recs, int64_t found, int64_t
   stc(c->sum_mf, sum_mf + mf);
   stc(c->reached, reached + found);
   for (int b = 0; b < 3; ++b) stc(c->qcnt[qcur][b], 0u);  // emptied for the level after
+  stc(c->qchunk[qcur], 0u);
   stc(c->qcur, nq);
   if (overflow) stc(c->overflow, 1);
   if (end) {
@@ -1159,6 +1181,7 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
     T.qcur = ldc(c->qcur);
     T.level = ldc(c->level);
     for (int b = 0; b < 3; ++b) T.cnt[b] = ld_agent(&c->qcnt[T.qcur][b]);
+    T.nchunk = ld_agent(&c->qchunk[T.qcur]);
     T.m_f = ldc(c->m_f);
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
@@ -1655,7 +1678,7 @@ __global__ void __launch_bounds__(1024) k_level(DevG<RowT> G, int32_t nb_small, 
     const int64_t a_s = min((int64_t)nb_small, (T.cnt[kSmall] + blockDim.x - 1) / blockDim.x);
     const int64_t m_items = T.cnt[kMedium] * medium_split(T.cnt[kMedium], (int64_t)nb_med * (blockDim.x >> 6), G.t2, T.m_f);
     const int64_t a_m = min((int64_t)nb_med, (m_items + (blockDim.x >> 6) - 1) / (blockDim.x >> 6));
-    const int64_t a_l = min(nb_large, T.cnt[kLarge]);
+    const int64_t a_l = min(nb_large, T.nchunk);
     int64_t r;
     if (b < nb_small) r = b < a_s ? b : -1;
     else if (b < nb_small + nb_med) r = b - nb_small < a_m ? a_s + (b - nb_small) : -1;
@@ -1893,7 +1916,8 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
       h.conv = kConvNone;
       h.qcnt[0][kSmall] = 1;
       h.qcnt[0][kMedium] = 1;
-      h.qcnt[0][kLarge] = g->max_degree > G.t2 ? (unsigned)((g->max_degree + G.t2 - 1) / G.t2) : 0;
+      h.qcnt[0][kLarge] = g->max_degree > G.t2 ? 1 : 0;
+      h.qchunk[0] = g->max_degree > G.t2 ? (unsigned)((g->max_degree + G.t2 - 1) / G.t2) : 0;
     } else if ((rc = wait_published(g, st, seq, &h))) {
       return rc;
     }
@@ -1909,7 +1933,7 @@ int host_loop(bfs_graph *g, const DevG<RowT> &G, hipStream_t st, std::vector<flo
     if (h.dir == kTD && h.conv == kConvB2Q) {  // frontier read from the bitmap, word-parallel
       launch_level(G, S, kTD, S.bu_blocks, TdRoles{0, 0, 0}, st, kExactLevel, level);
     } else if (h.dir == kTD) {
-      const TdRoles r = td_roles(S, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qcnt[h.qcur][2], G.t2);
+      const TdRoles r = td_roles(S, h.qcnt[h.qcur][0], h.qcnt[h.qcur][1], h.qchunk[h.qcur], G.t2);
       launch_level(G, S, kTD, r.small + r.med + r.large, r, st, kExactLevel, level);
     } else {
       launch_level(G, S, kBU, S.bu_blocks, TdRoles{0, 0, 0}, st, kExactLevel, level);

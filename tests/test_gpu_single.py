@@ -82,6 +82,24 @@ def test_threshold_sweep(bfs, rmat16, t1, t2, tbu, bs):
     gh.close()
 
 
+@pytest.mark.parametrize("loop", [1, 2, 3])
+def test_large_queue_windows(bfs, rmat16, loop):
+    """Top-down-only searches with a low large-vertex threshold (t2 = 64) and
+    64-thread workgroups: a level queues hundreds of large vertices (one
+    entry each, with its chunk count), which the large role reads in many
+    64-entry windows and splits into chunks round-robin over its
+    workgroups; distances, parents and every level record equal the
+    oracle's, in the host, captured and persistent loops."""
+    g = rmat16
+    say("rmat16 large-queue windows, loop", loop)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, policy=3, loop=loop, td_wave_degree=8, td_block_degree=64, block_size=64,
+                       graph_td_blocks=16)
+    for s in graphgen.sources(g, 3, seed=21):
+        check_single(g, gh, s)
+    gh.close()
+
+
 def test_repeat_identical(bfs, rmat16):
     g = rmat16
     say("rmat16 repeat x20")
