@@ -615,6 +615,8 @@ def main():
     ap.add_argument("--levels-json", default=None,
                     help="write the instrumented pass's per-level records of every search to this file "
                          "(the last --steps passes over the sources, in launch order)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the serving section (12-graph pool)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched section (RMAT-22, 64 sources), e.g. to profile its kernel")
     args = ap.parse_args()
@@ -642,6 +644,9 @@ def main():
     from paper_2503_00430_amd import autotune
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.serving_only:
+        print(json.dumps({"serving": bench_serving(bfs, torch)}), flush=True)
+        return
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(bfs, torch, cpu=False)}), flush=True)
         return
