@@ -674,8 +674,16 @@ int issue_chunk(Batch *b, int levels) {
   return BFS_OK;
 }
 
-int chunk_levels(const bfs_graph *g) {
-  return g->nnz < 7 * g->n ? 32 : 4;  // large-diameter class: longer chunks
+// Levels per issued chunk.  Large-diameter graphs run long chunks (their
+// levels are many and cheap, and every chunk boundary is a host round trip),
+// but only while no other batch is active and no other graph's request
+// waits: the streams of different batches share the device's few hardware
+// queues, and a chunk of a thousands-of-levels search ahead of another
+// batch's kernels would hold those back for its whole length.
+constexpr int kSvSharedChunk = 8;
+int chunk_levels(const bfs_graph *g, bool shared) {
+  if (g->nnz < 7 * g->n) return shared ? kSvSharedChunk : 32;  // large-diameter class
+  return 4;
 }
 
 }  // namespace
@@ -763,9 +771,19 @@ void evict_idle(bfs_server *s, size_t need) {
   }
 }
 
-int issue(Batch *b) {
+// True when a batch other than `b` is running or a request of another
+// graph is waiting.
+bool others_busy(const bfs_server *s, const Batch *b) {
+  for (const auto &o : s->batches)
+    if (o.get() != b && (o->active || o->in_flight)) return true;
+  for (const auto &w : s->waiting)
+    if (w.first != b->g && !w.second.empty()) return true;
+  return !s->inbox.empty();
+}
+
+int issue(bfs_server *s, Batch *b) {
   DeviceGuard dg(b->g->device);
-  const int lv = chunk_levels(b->g);
+  const int lv = chunk_levels(b->g, others_busy(s, b));
   return b->g->rp64 ? issue_chunk<int64_t>(b, lv) : issue_chunk<int32_t>(b, lv);
 }
 
@@ -794,7 +812,7 @@ void worker_loop(bfs_server *s) {
       }
       admit(s, b);
       if (b->active) {
-        if (issue(b) != BFS_OK) fail_batch(s, b, bfs_last_error());
+        if (issue(s, b) != BFS_OK) fail_batch(s, b, bfs_last_error());
         busy = busy || b->in_flight;
       }
       ++k;  // an empty batch stays allocated for the next request of its graph
@@ -827,7 +845,7 @@ void worker_loop(bfs_server *s) {
       s->batches.push_back(std::move(nb));
       admit(s, b);  // may erase `it`'s entry
       it = s->waiting.lower_bound(g);
-      if (issue(b) != BFS_OK) fail_batch(s, b, bfs_last_error());
+      if (issue(s, b) != BFS_OK) fail_batch(s, b, bfs_last_error());
       busy = true;
     }
     bool running = false;
