@@ -49,7 +49,10 @@ struct alignas(256) Ctl {
   int32_t overflow; // nonzero: a level appended more entries than a queue holds
                     // (entries past the end were dropped; the search stops)
   int32_t classless; // DevG::classless of this search
+  int32_t sum_ok[2];  // nonzero: summary s has a bit for every word of bitmap s
+                      // that holds a frontier vertex (bottom-up levels may test it)
   int64_t n;        // vertex count
+  int64_t nnz;      // adjacency entries (twice the undirected edges)
   int64_t n_f;      // size of the current frontier
   int64_t m_f;      // sum of degrees over the current frontier
   int64_t m_u;      // sum of degrees over vertices not yet visited

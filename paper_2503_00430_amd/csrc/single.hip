@@ -368,9 +368,12 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->qcap[0] = G.qcap;
     c->qcap[1] = G.lcap;
     c->n = G.n;
+    c->nnz = nnz;
     c->n_f = 1;
     // (classless searches add a level's m_f up while expanding it)
     c->classless = G.classless;
+    c->sum_ok[0] = 1;
+    c->sum_ok[1] = 1;
     c->m_f = G.classless ? 0 : deg;
     c->m_u = G.classless ? nnz : nnz - deg;
     c->sum_mf = 0;
@@ -399,6 +402,23 @@ __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, 
     c->seq = seq0;  // publication numbers continue across runs, so a stale
     publish(c);     // mirror never matches the number a new run waits for
   }
+}
+
+// A bottom-up level copies the frontier summary into LDS when the frontier
+// has at most this many vertices per bitmap word.
+constexpr int64_t kSumFrontierWords = 2;
+
+// A top-down level keeps the occupancy summary of the frontier bitmap only
+// while the frontier it makes could be small enough for a bottom-up level to
+// test the summary.  Its expected size is the level's edges times the share
+// of edge ends not yet visited, m_f * m_u / nnz; where that is more than
+// twice the bottom-up level's limit, the level skips the summary's atomics
+// (on a hub-heavy level a third of its memory-side atomics), and the
+// summary counts as incomplete until a bottom-up level has rewritten it.
+// The top-down level and the decide step evaluate this with the same
+// values (the control block's m_f and m_u before the decide step).
+__host__ __device__ inline bool td_keeps_summary(int64_t m_f, int64_t m_u, int64_t n, int64_t nnz) {
+  return (double)m_f * (double)m_u <= (double)(2 * kSumFrontierWords) * (double)((n + 63) >> 6) * (double)nnz;
 }
 
 // Moves the control block's level number on with an agent-scope atomic
@@ -453,6 +473,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     for (int b = 0; b < 3; ++b) c->qcnt[c->qcur][b] = 0;
     c->qchunk[c->qcur] = 0;
     c->qcur ^= 1;
+    if (!td_keeps_summary(mf, c->m_u, c->n, c->nnz)) c->sum_ok[c->bcur] = 0;  // it skipped its summary bits
     // with the visited test of plain loads and stores a vertex can be
     // appended once per racing discoverer; a set that outgrew its queues
     // lost entries, so the search ends here and the host reports it
@@ -467,6 +488,7 @@ __device__ void decide_apply(Ctl *c, LevelRec *recs, const unsigned long long (&
     }
   } else {
     c->bcur ^= 1;
+    c->sum_ok[c->bcur] = 1;  // written whole by the level (read only where it was)
   }
   if (found == 0) {
     c->done = 1;
@@ -654,7 +676,8 @@ __device__ __forceinline__ TdLevel td_level_state(const DevG<RowT> &G, const Ctl
   t.dist = c->dist;
   t.parent = c->parent;
   t.fbm = c->policy != BFS_POLICY_TD_ONLY ? (c->bcur ? G.bm[1] : G.bm[0]) : nullptr;
-  t.fsm = (t.fbm && G.sshift >= 0) ? (c->bcur ? G.sm[1] : G.sm[0]) : nullptr;
+  t.fsm = (t.fbm && G.sshift >= 0 && td_keeps_summary(t.m_f, c->m_u, c->n, c->nnz)) ? (c->bcur ? G.sm[1] : G.sm[0])
+                                                                                     : nullptr;
   t.sshift = G.sshift;
   t.from_bitmap = c->conv == kConvB2Q;
   return t;
@@ -863,8 +886,10 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
         const int64_t end = min(row_end, beg + (int64_t)G.t2);
         // kTdUnroll neighbours per lane per step, each step's ids coalesced;
         // the steps are workgroup-uniform, and the staging buffers are
-        // emptied after each one (a hub's neighbours are themselves of high
-        // degree: without that, their entries would overflow to the global
+        // emptied after a step that leaves one of them at least half full (a
+        // step stages at most kTdUnroll entries per thread, so the small and
+        // medium buffers never overflow; a hub's neighbours are themselves of
+        // high degree, and entries past a full buffer would go to the global
         // queue with one contended atomic per wavefront)
         for (int64_t step = beg; step < end; step += (int64_t)blockDim.x * kTdUnroll) {
           const int64_t bb = step + wib * kWave * kTdUnroll;
@@ -876,7 +901,7 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
             uu[qq] = u;
           }
           td_claim_batch<kTdUnroll>(G, S, T, qn, x, uu, nfound, dfound);
-          stage_flush(G, S, qn);
+          stage_flush(G, S, qn, true);
         }
       }
       cbase += tot;
@@ -1288,9 +1313,6 @@ struct BuWaveLds {
 
 __host__ __device__ constexpr size_t bu_lds_bytes(int bs) { return (size_t)(bs / kWave) * sizeof(BuWaveLds); }
 
-// A bottom-up level copies the frontier summary into LDS when the frontier
-// has at most this many vertices per bitmap word.
-constexpr int64_t kSumFrontierWords = 2;
 
 // The frontier bitmap a bottom-up level tests, and optionally an LDS copy
 // of its occupancy summary: a neighbour whose word's summary bit is clear is
@@ -1543,7 +1565,7 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
   front.bits = reinterpret_cast<const uint32_t *>(bcur ? G.bm[1] : G.bm[0]);
   front.lsum = nullptr;
   front.sshift = G.sshift;
-  if (sums && n_f <= kSumFrontierWords * G.words) {
+  if (sums && n_f <= kSumFrontierWords * G.words && c->sum_ok[bcur]) {
     uint64_t *lsum = reinterpret_cast<uint64_t *>(lds + bu_lds_bytes(blockDim.x));
     const uint64_t *fsm = bcur ? G.sm[1] : G.sm[0];
     for (int i = threadIdx.x; i < G.swords; i += blockDim.x) lsum[i] = fsm[i];
@@ -1672,23 +1694,23 @@ __global__ void __launch_bounds__(1024) k_level(DevG<RowT> G, int32_t nb_small, 
       end_level<kPartials>(G, mode, counts, rank, nactive, T.level);
       return;
     }
-    // only the workgroups whose role has work this level take part
+    // Only the workgroups whose role has work this level take part: the
+    // small and medium roles as many as their queues need (at most nb_small
+    // and nb_med; each then covers its queue in one round), the per-chunk
+    // role every other workgroup of the grid, up to one per chunk.  The
+    // roles take consecutive workgroups in that order.
     const int64_t b = blockIdx.x;
-    const int64_t nb_large = (int64_t)gridDim.x - nb_small - nb_med;
+    const int64_t wpb = blockDim.x >> 6;
     const int64_t a_s = min((int64_t)nb_small, (T.cnt[kSmall] + blockDim.x - 1) / blockDim.x);
-    const int64_t m_items = T.cnt[kMedium] * medium_split(T.cnt[kMedium], (int64_t)nb_med * (blockDim.x >> 6), G.t2, T.m_f);
-    const int64_t a_m = min((int64_t)nb_med, (m_items + (blockDim.x >> 6) - 1) / (blockDim.x >> 6));
-    const int64_t a_l = min(nb_large, T.nchunk);
-    int64_t r;
-    if (b < nb_small) r = b < a_s ? b : -1;
-    else if (b < nb_small + nb_med) r = b - nb_small < a_m ? a_s + (b - nb_small) : -1;
-    else r = b - nb_small - nb_med < a_l ? a_s + a_m + (b - nb_small - nb_med) : -1;
-    if (r < 0) return;  // uniform over the workgroup
-    rank = (unsigned)r;
+    const int64_t m_items = T.cnt[kMedium] * medium_split(T.cnt[kMedium], (int64_t)nb_med * wpb, G.t2, T.m_f);
+    const int64_t a_m = min((int64_t)nb_med, (m_items + wpb - 1) / wpb);
+    const int64_t a_l = min((int64_t)gridDim.x - a_s - a_m, T.nchunk);
+    if (b >= a_s + a_m + a_l) return;  // uniform over the workgroup
+    rank = (unsigned)b;
     nactive = (unsigned)(a_s + a_m + a_l);
     const Stage S = stage_open(lds);
     unsigned long long tc[2];
-    td_level(G, T, S, blockIdx.x, gridDim.x, nb_small, nb_med, tc);
+    td_level(G, T, S, blockIdx.x, gridDim.x, (int)a_s, (int)a_m, tc);
     counts[0] = tc[0];
     counts[1] = tc[1];
   } else {
