@@ -176,6 +176,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="rmat22",
                     help="rmatS (scale S), gridW (W x W lattice) or urandD (2^20 vertices, degree D)")
     ap.add_argument("--sources", type=int, default=16)
+    ap.add_argument("--source-seed", type=int, default=None,
+                    help="seed of the source sample (default: the generator's own, as the benchmark draws)")
     ap.add_argument("--modes", default="single,batch")
     ap.add_argument("--out", default=DEFAULT_FILE)
     ap.add_argument("--flags", type=lambda x: int(x, 0), default=L.BFS_SORT_NEIGHBORS,
@@ -194,7 +196,7 @@ def main(argv=None):
         cg = graphgen.urand(1 << 20, int(w[5:]))
     else:
         raise SystemExit(f"unknown workload {w}")
-    srcs = graphgen.sources(cg, args.sources)
+    srcs = graphgen.sources(cg, args.sources, seed=args.source_seed)
     g = L.bfs_create_graph(cg.row_ptr, cg.col_idx, args.flags)
     info = L.bfs_graph_info_get(g)
     tuned = {}
