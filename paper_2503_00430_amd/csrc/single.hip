@@ -1365,9 +1365,14 @@ __device__ __forceinline__ void bu_found(BuWaveLds &W, int32_t v, int32_t deg, i
 // `head` past their head records.  The rows' remaining neighbours are laid
 // end to end and read 64 at a time, a lane per neighbour, so a step reads
 // whole stretches of rows whatever their lengths (one row per lane would take
-// as many steps as the longest row needs while the other lanes idle).  Each
-// row takes its first frontier neighbour in row order; lanes of a row that
-// has already hit read nothing more.  Records the finds.
+// as many steps as the longest row needs while the other lanes idle).  The
+// neighbour ids of kDrainSteps such steps are loaded before any of them is
+// tested, so a wavefront has that many steps' loads in flight instead of
+// one.  Each row takes its first frontier neighbour in row order (steps in
+// order, then lanes); lanes of a row that had already hit when the steps
+// were loaded read nothing more.  Records the finds.
+constexpr int kDrainSteps = 2;
+
 template <class RowT>
 __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsigned head, unsigned cnt,
                                          const Front &front, int64_t sr, int32_t level, int32_t *dist,
@@ -1394,37 +1399,46 @@ __device__ __forceinline__ void bu_drain(const DevG<RowT> &G, BuWaveLds &W, unsi
   bool found = false;
   int32_t hit = -1, ex = deg;
   const uint64_t upto = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;  // lanes <= this one
-  for (int32_t p = 0; p < total; p += kWave) {  // uniform
-    // position p + lane belongs to the last row that starts at or before it
-    const bool starts = act && off >= p && off < p + kWave;
-    const uint64_t sbits = wave_or(starts ? 1ull << (off - p) : 0ull);
-    const int r = __popcll(__ballot(act && off < p)) + __popcll(sbits & upto) - 1;
-    const int32_t e = p + lane;
-    const int64_t rfrom = __shfl(from, r);
-    const int32_t roff = __shfl(off, r);
-    const bool rdone = __shfl((int)found, r) != 0;
-    int32_t x = -1;
-    bool h = false;
-    if (e < total && !rdone) {
-      x = G.col[rfrom + (e - roff)];
-      h = front_bit(front, x);
+  for (int32_t p0 = 0; p0 < total; p0 += kWave * kDrainSteps) {  // uniform
+    int32_t x[kDrainSteps];
+    bool h[kDrainSteps];
+    const bool done0 = found;  // rows that hit in an earlier round read nothing more
+#pragma unroll
+    for (int u = 0; u < kDrainSteps; ++u) {
+      // position p + lane belongs to the last row that starts at or before it
+      const int32_t p = p0 + u * kWave;
+      const bool starts = act && off >= p && off < p + kWave;
+      const uint64_t sbits = wave_or(starts ? 1ull << (off - p) : 0ull);
+      const int r = __popcll(__ballot(act && off < p)) + __popcll(sbits & upto) - 1;
+      const int32_t e = p + lane;
+      const int64_t rfrom = __shfl(from, r);
+      const int32_t roff = __shfl(off, r);
+      const bool rdone = __shfl((int)done0, r) != 0;
+      x[u] = -1;
+      if (e < total && !rdone) x[u] = G.col[rfrom + (e - roff)];
     }
-    const uint64_t hm = __ballot(h);
-    // each unfinished row takes the first hit within its own lanes
-    int f = -1;
-    if (act && !found) {
-      const int32_t lo = max(off, p) - p, hi = min(off + len, p + kWave) - p;  // its lanes [lo, hi)
-      if (lo < hi) {
-        const uint64_t seg = (hi == kWave ? ~0ull : (1ull << hi) - 1) & ~((1ull << lo) - 1);
-        const uint64_t mh = hm & seg;
-        if (mh) f = __builtin_ctzll(mh);
+#pragma unroll
+    for (int u = 0; u < kDrainSteps; ++u) h[u] = x[u] >= 0 && front_bit(front, x[u]);
+#pragma unroll
+    for (int u = 0; u < kDrainSteps; ++u) {
+      const int32_t p = p0 + u * kWave;
+      const uint64_t hm = __ballot(h[u]);
+      // each unfinished row takes the first hit within its own lanes
+      int f = -1;
+      if (act && !found) {
+        const int32_t lo = max(off, p) - p, hi = min(off + len, p + kWave) - p;  // its lanes [lo, hi)
+        if (lo < hi) {
+          const uint64_t seg = (hi == kWave ? ~0ull : (1ull << hi) - 1) & ~((1ull << lo) - 1);
+          const uint64_t mh = hm & seg;
+          if (mh) f = __builtin_ctzll(mh);
+        }
       }
-    }
-    const int32_t xf = __shfl(x, f < 0 ? 0 : f);
-    if (f >= 0) {
-      found = true;
-      hit = xf;
-      ex = 3 + (p + f - off) + 1;
+      const int32_t xf = __shfl(x[u], f < 0 ? 0 : f);
+      if (f >= 0) {
+        found = true;
+        hit = xf;
+        ex = 3 + (p + f - off) + 1;
+      }
     }
   }
   if (act) C.exam += (unsigned long long)ex;
@@ -1453,20 +1467,25 @@ __device__ __forceinline__ void bu_long_rows(const DevG<RowT> &G, BuWaveLds &W, 
     const int64_t e0 = r0 + __shfl(deg, l);
     int64_t exl = e0 - r0;
     int32_t hitl = -1;
-    for (int64_t b = r0 + 3; b < e0; b += kWave) {
-      const int64_t j = b + lane;
-      int32_t x = 0;
-      bool h = false;
-      if (j < e0) {
-        x = G.col[j];
-        h = front_bit(front, x);
+    // kDrainSteps steps of 64 neighbours loaded, then tested in order
+    for (int64_t b0 = r0 + 3; b0 < e0 && hitl < 0; b0 += (int64_t)kWave * kDrainSteps) {  // uniform
+      int32_t x[kDrainSteps];
+#pragma unroll
+      for (int u = 0; u < kDrainSteps; ++u) {
+        const int64_t j = b0 + u * kWave + lane;
+        x[u] = j < e0 ? G.col[j] : -1;
       }
-      const uint64_t hb = __ballot(h);
-      if (hb) {
-        const int f = __ffsll((unsigned long long)hb) - 1;
-        hitl = __shfl(x, f);
-        exl = b - r0 + f + 1;
-        break;
+      bool h[kDrainSteps];
+#pragma unroll
+      for (int u = 0; u < kDrainSteps; ++u) h[u] = x[u] >= 0 && front_bit(front, x[u]);
+#pragma unroll
+      for (int u = 0; u < kDrainSteps; ++u) {
+        const uint64_t hb = __ballot(h[u]);
+        if (hb && hitl < 0) {  // uniform
+          const int f = __ffsll((unsigned long long)hb) - 1;
+          hitl = __shfl(x[u], f);
+          exl = b0 + u * kWave - r0 + f + 1;
+        }
       }
     }
     if (lane == l) {
