@@ -1297,8 +1297,13 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
 //      visited words with one coalesced store per run.
 // `examined` counts neighbours up to and including the first hit.
 constexpr int kBuUnroll = 4;
-constexpr int kCand = 128;  // candidate ring: < 64 waiting + 64 from one word
-constexpr int kDefer = 128;  // deferred ring: < 64 waiting + 64 from one batch
+// A bottom-up wavefront resolves its candidates kBuSub * 64 at a time (lane
+// l holds candidates l, l + 64, ...), so the frontier-word gathers of kBuSub
+// batches are in flight together.
+constexpr int kBuSub = 2;
+constexpr int kBuBatch = kBuSub * kWave;
+constexpr int kCand = 256;  // candidate ring: < kBuBatch waiting + 64 from one word
+constexpr int kDefer = 128;  // deferred ring: < 64 waiting + 64 from one sub-batch
 
 struct BuWaveLds {
   int32_t cand[kCand];
@@ -1500,58 +1505,74 @@ __device__ __forceinline__ void bu_long_rows(const DevG<RowT> &G, BuWaveLds &W, 
   if (found) bu_found<RowT>(W, v, deg, hit, sr, level, dist, parent, C);
 }
 
-// Resolves one batch of `cnt` candidates (lane < cnt holds vertex v with
-// head record h): tests the head neighbours, records the finds, scans rows
-// longer than tbu at once and defers the rest of the longer rows (draining
-// 64 deferred rows when that many wait, and every deferred row after the
-// `last` batch of a run).
+// Resolves one batch of `cnt` (<= kBuBatch) candidates (candidate
+// k * 64 + lane is vertex v[k] with head record h[k] in lane `lane`): tests
+// the head neighbours of all of them together, then, sub-batch by sub-batch,
+// records the finds, scans rows longer than tbu at once and defers the rest
+// of the longer rows (draining 64 deferred rows when that many wait, and
+// every deferred row after the `last` batch of a run).
 template <class RowT>
-__device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, int32_t v, int32_t cr, const int4 h, int cnt,
+__device__ __forceinline__ void bu_resolve(const DevG<RowT> &G, BuWaveLds &W, const int32_t (&v)[kBuSub],
+                                           const int32_t (&cr)[kBuSub], const int4 (&h)[kBuSub], int cnt,
                                            const Front &front, int64_t sr, int32_t level, int32_t *dist,
                                            int32_t *parent, unsigned &dh, unsigned &dc, bool last, BuCount &C) {
   const int lane = lane_id();
-  const bool act = lane < cnt;
+  bool act[kBuSub];
+#pragma unroll
+  for (int k = 0; k < kBuSub; ++k) act[k] = lane + k * kWave < cnt;
   // the second and third head neighbours are tested only where the first
   // misses (with hub-first rows most finds are at the first, and the
   // frontier-bit gathers are the level's largest request count)
-  uint32_t f0 = 0, f1 = 0, f2 = 0;
-  if (act) f0 = front_word(front, h.y);  // degree >= 1: the first neighbour exists
-  if (act && !((f0 >> (h.y & 31)) & 1u)) {
-    if (h.z >= 0) f1 = front_word(front, h.z);
-    if (h.w >= 0) f2 = front_word(front, h.w);
+  uint32_t f0[kBuSub], f1[kBuSub], f2[kBuSub];
+#pragma unroll
+  for (int k = 0; k < kBuSub; ++k) {
+    f0[k] = f1[k] = f2[k] = 0;
+    if (act[k]) f0[k] = front_word(front, h[k].y);  // degree >= 1: the first neighbour exists
   }
-  bool found = false, defer = false, longrow = false;
-  int32_t hit = -1;
-  if (act) {
-    int32_t ex = h.x;
-    if ((f0 >> (h.y & 31)) & 1u) {
-      found = true; hit = h.y; ex = 1;
-    } else if (h.z >= 0 && ((f1 >> (h.z & 31)) & 1u)) {
-      found = true; hit = h.z; ex = 2;
-    } else if (h.w >= 0 && ((f2 >> (h.w & 31)) & 1u)) {
-      found = true; hit = h.w; ex = 3;
-    } else if (h.x > 3) {
-      (h.x > G.tbu ? longrow : defer) = true;  // counted when its row is scanned
+#pragma unroll
+  for (int k = 0; k < kBuSub; ++k) {
+    if (act[k] && !((f0[k] >> (h[k].y & 31)) & 1u)) {
+      if (h[k].z >= 0) f1[k] = front_word(front, h[k].z);
+      if (h[k].w >= 0) f2[k] = front_word(front, h[k].w);
     }
-    if (!defer && !longrow) C.exam += (unsigned long long)ex;
-    C.scan += 1;
   }
-  if (found) bu_found<RowT>(W, v, h.x, hit, sr, level, dist, parent, C);
-  const uint64_t lm = __ballot(longrow);
-  if (lm) bu_long_rows(G, W, lm, v, h.x, front, sr, level, dist, parent, C);
-  const uint64_t dm = __ballot(defer);
-  if (defer) {
-    const unsigned slot = (dh + dc + lanes_below(dm)) & (kDefer - 1);
-    W.dv[slot] = v;
-    W.ddeg[slot] = h.x;
-    W.dcr[slot] = cr;
-  }
-  dc += (unsigned)__popcll(dm);
-  while (dc >= kWave || (last && dc > 0)) {  // uniform; the last batch may leave up to 127
-    const unsigned n = dc < kWave ? dc : kWave;
-    bu_drain(G, W, dh, n, front, sr, level, dist, parent, C);
-    dh = (dh + n) & (kDefer - 1);
-    dc -= n;
+#pragma unroll
+  for (int k = 0; k < kBuSub; ++k) {
+    bool found = false, defer = false, longrow = false;
+    int32_t hit = -1;
+    const int4 hk = h[k];
+    if (act[k]) {
+      int32_t ex = hk.x;
+      if ((f0[k] >> (hk.y & 31)) & 1u) {
+        found = true; hit = hk.y; ex = 1;
+      } else if (hk.z >= 0 && ((f1[k] >> (hk.z & 31)) & 1u)) {
+        found = true; hit = hk.z; ex = 2;
+      } else if (hk.w >= 0 && ((f2[k] >> (hk.w & 31)) & 1u)) {
+        found = true; hit = hk.w; ex = 3;
+      } else if (hk.x > 3) {
+        (hk.x > G.tbu ? longrow : defer) = true;  // counted when its row is scanned
+      }
+      if (!defer && !longrow) C.exam += (unsigned long long)ex;
+      C.scan += 1;
+    }
+    if (found) bu_found<RowT>(W, v[k], hk.x, hit, sr, level, dist, parent, C);
+    const uint64_t lm = __ballot(longrow);
+    if (lm) bu_long_rows(G, W, lm, v[k], hk.x, front, sr, level, dist, parent, C);
+    const uint64_t dm = __ballot(defer);
+    if (defer) {
+      const unsigned slot = (dh + dc + lanes_below(dm)) & (kDefer - 1);
+      W.dv[slot] = v[k];
+      W.ddeg[slot] = hk.x;
+      W.dcr[slot] = cr[k];
+    }
+    dc += (unsigned)__popcll(dm);
+    // (fewer than 64 wait after this, so the next sub-batch fits the ring)
+    while (dc >= kWave || (last && k == kBuSub - 1 && dc > 0)) {  // uniform
+      const unsigned n = dc < kWave ? dc : kWave;
+      bu_drain(G, W, dh, n, front, sr, level, dist, parent, C);
+      dh = (dh + n) & (kDefer - 1);
+      dc -= n;
+    }
   }
 }
 
@@ -1603,8 +1624,14 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
     unsigned ch = 0, ct = 0;                   // candidate ring head / tail (uniform)
     unsigned dh = 0, dc = 0;                   // deferred ring head / count
     int pc = 0;                                // candidates of the batch in flight
-    int32_t pv = 0, pcr = 0;
-    int4 ph = make_int4(0, 0, -1, -1);
+    int32_t pv[kBuSub], pcr[kBuSub];
+    int4 ph[kBuSub];
+#pragma unroll
+    for (int k = 0; k < kBuSub; ++k) {
+      pv[k] = 0;
+      pcr[k] = 0;
+      ph[k] = make_int4(0, 0, -1, -1);
+    }
     for (;;) {
       if (act) {
         const int k = __builtin_ctzll(act);
@@ -1618,24 +1645,33 @@ __device__ __forceinline__ void bu_level(const DevG<RowT> &G, const Ctl *c, char
           W.crank[slot] = (int32_t)(W.rank[k] + lanes_below(W.live[k]));
         }
         ct += (unsigned)__popcll(un);
-        if (ct - ch < (unsigned)kWave && act) continue;  // uniform
+        if (ct - ch < (unsigned)kBuBatch && act) continue;  // uniform
       }
       // next batch: load its head records, then resolve the one in flight
       // (an empty next batch marks the run's last resolve)
-      const int cnt = (int)min(ct - ch, (unsigned)kWave);
+      const int cnt = (int)min(ct - ch, (unsigned)kBuBatch);
       if (cnt == 0 && pc == 0) break;
-      int32_t bv = 0, bcr = 0;
-      int4 bh = make_int4(0, 0, -1, -1);
-      if (lane < cnt) {
-        bv = W.cand[(ch + lane) & (kCand - 1)];
-        bcr = W.crank[(ch + lane) & (kCand - 1)];
-        bh = G.headc[bcr];
+      int32_t bv[kBuSub], bcr[kBuSub];
+      int4 bh[kBuSub];
+#pragma unroll
+      for (int k = 0; k < kBuSub; ++k) {
+        bv[k] = 0;
+        bcr[k] = 0;
+        bh[k] = make_int4(0, 0, -1, -1);
+        if (lane + k * kWave < cnt) {
+          bv[k] = W.cand[(ch + k * kWave + lane) & (kCand - 1)];
+          bcr[k] = W.crank[(ch + k * kWave + lane) & (kCand - 1)];
+          bh[k] = G.headc[bcr[k]];
+        }
       }
       ch += cnt;
       if (pc) bu_resolve(G, W, pv, pcr, ph, pc, front, sr, level, dist, parent, dh, dc, cnt == 0, C);
-      pv = bv;
-      pcr = bcr;
-      ph = bh;
+#pragma unroll
+      for (int k = 0; k < kBuSub; ++k) {
+        pv[k] = bv[k];
+        pcr[k] = bcr[k];
+        ph[k] = bh[k];
+      }
       pc = cnt;
     }
     // one coalesced store of the run's next-frontier and visited words
