@@ -131,7 +131,7 @@ static void destroy(bfs_graph *g) {
   DeviceGuard dg(g->device);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   release_graph_exec(g);
-  void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->headc, g->hrank, g->rpc, g->vis, g->bm[0], g->bm[1], g->sm[0], g->sm[1], g->qs[0], g->qs[1],
+  void *ptrs[] = {g->rp, g->col, g->iso, g->head, g->headc, g->nb4, g->hrank, g->rpc, g->vis, g->bm[0], g->bm[1], g->sm[0], g->sm[1], g->qs[0], g->qs[1],
                   g->qm[0], g->qm[1], g->ql[0], g->ql[1], g->slot, g->ctl, g->recs, g->partials,
                   g->ms.seen, g->ms.front, g->ms.next, g->ms.counters, g->ms.hq, g->ms.planes};
   for (void *p : ptrs) free_dev(p);
@@ -338,6 +338,7 @@ int bfs_create_graph(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32
   ALLOC(g->iso, g->words);
   ALLOC(g->head, n);
   ALLOC(g->headc, std::max<int64_t>(1, n - g->isolated));
+  if (g->max_degree <= 4) ALLOC(g->nb4, n);
   if (nnz < ((int64_t)1 << 32)) ALLOC(g->rpc, std::max<int64_t>(1, n - g->isolated));
   ALLOC(g->hrank, g->words);
   ALLOC(g->vis, g->words);

@@ -101,6 +101,8 @@ struct DevG {
   const uint64_t *iso;  // bit set: vertex has degree 0, or id >= n (tail of last word)
   const int4 *head;     // per vertex: {degree, first three neighbours or -1}
   const int4 *headc;    // the same records for the non-isolated vertices only, in id order
+  const int4 *nb4;      // graphs of maximum degree <= 4: per vertex all four neighbours
+                        // (-1 past the row's end), else null
   const uint32_t *hrank;  // per word: non-isolated vertices in the words before it
   const uint32_t *rpc;  // row offsets of the non-isolated vertices in headc order (null
                         // when nnz >= 2^32: then rp is read)
@@ -154,6 +156,7 @@ struct bfs_graph {
   uint64_t *iso = nullptr;
   int4 *head = nullptr;  // {degree, first three neighbours or -1} per vertex
   int4 *headc = nullptr;  // head records of the non-isolated vertices only, in id order
+  int4 *nb4 = nullptr;    // maximum degree <= 4: all four neighbours per vertex (-1 past the end)
   uint32_t *hrank = nullptr;  // per word: count of non-isolated vertices in earlier words
   uint32_t *rpc = nullptr;  // row offsets in headc order (allocated when nnz < 2^32)
   uint64_t *vis = nullptr;

@@ -806,15 +806,28 @@ __device__ __forceinline__ void td_level(const DevG<RowT> &G, const TdLevel &T, 
       bool act = i < cnt;
       const int32_t u = act ? ld_x(q + i, G.pers) : 0;
       if (act && G.slot) act = ld_x(G.slot + u, G.pers) == (int32_t)i;  // culled duplicate: expand only the recorded copy
-      int4 h = make_int4(0, -1, -1, -1);
-      int64_t row0 = 0;
-      if (act) {
-        h = G.head[u];  // degree and first three neighbours
-        if (G.classless) dfound += (unsigned long long)h.x;  // this level's m_f
-        row0 = (int64_t)G.rp[u];  // issued together with the head load
-        fbm_clear(T.fbm, u);
+      if (G.nb4) {  // rows of at most four: the whole row in one record
+        int4 r4 = make_int4(-1, -1, -1, -1);
+        if (act) {
+          r4 = G.nb4[u];
+          if (G.classless)  // this level's m_f
+            dfound += (unsigned long long)((r4.x >= 0) + (r4.y >= 0) + (r4.z >= 0) + (r4.w >= 0));
+          fbm_clear(T.fbm, u);
+        }
+        const int32_t x[4] = {r4.x, r4.y, r4.z, r4.w};
+        const int32_t uu[4] = {u, u, u, u};
+        td_claim_batch<4>(G, S, T, qn, x, uu, nfound, dfound);
+      } else {
+        int4 h = make_int4(0, -1, -1, -1);
+        int64_t row0 = 0;
+        if (act) {
+          h = G.head[u];  // degree and first three neighbours
+          if (G.classless) dfound += (unsigned long long)h.x;  // this level's m_f
+          row0 = (int64_t)G.rp[u];  // issued together with the head load
+          fbm_clear(T.fbm, u);
+        }
+        td_expand_lane(G, S, T, qn, act, u, h, row0, nfound, dfound);
       }
-      td_expand_lane(G, S, T, qn, act, u, h, row0, nfound, dfound);
       stage_flush(G, S, qn, true);
     }
   } else if (blk < nb_small + nb_med) {
@@ -1201,13 +1214,22 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
   unsigned long long *arrive = G.partials + kArriveOffset;       // (found << 11) + arrivals
   uint32_t *gen = reinterpret_cast<uint32_t *>(G.partials + kArriveOffset + kLineU64);  // levels released
   for (int64_t it = 0; it <= G.n; ++it) {
-    if (ldc(c->done)) break;  // uniform: read after the release every workgroup saw
+    // The level's state in one round of loads (read after the release every
+    // workgroup saw): both queue sets' counts are read and the current one
+    // selected, so no load waits for another.
+    const int32_t done = ldc(c->done);
     TdLevel T;
     T.qcur = ldc(c->qcur);
     T.level = ldc(c->level);
-    for (int b = 0; b < 3; ++b) T.cnt[b] = ld_agent(&c->qcnt[T.qcur][b]);
-    T.nchunk = ld_agent(&c->qchunk[T.qcur]);
     T.m_f = ldc(c->m_f);
+    unsigned q[2][3], qch[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+      for (int b = 0; b < 3; ++b) q[s2][b] = ld_agent(&c->qcnt[s2][b]);
+      qch[s2] = ld_agent(&c->qchunk[s2]);
+    }
+    if (done) break;  // uniform
+    for (int b = 0; b < 3; ++b) T.cnt[b] = T.qcur ? q[1][b] : q[0][b];
+    T.nchunk = T.qcur ? qch[1] : qch[0];
     T.dist = c->dist;  // constant for the whole search
     T.parent = c->parent;
     T.fbm = nullptr;  // top-down only: no frontier bitmap to keep
@@ -1785,12 +1807,13 @@ __global__ void __launch_bounds__(1024) k_level(DevG<RowT> G, int32_t nb_small, 
 // shorter), so short rows and most bottom-up hits need one coalesced 16-byte
 // load instead of a row-offset pair and a neighbour-id line.
 template <class RowT>
-__global__ void k_build_head(const RowT *rp, const int32_t *col, int4 *head, int64_t n) {
+__global__ void k_build_head(const RowT *rp, const int32_t *col, int4 *head, int4 *nb4, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int64_t b = (int64_t)rp[v], e = (int64_t)rp[v + 1];
-    head[v] = make_int4((int)(e - b), b < e ? col[b] : -1, b + 1 < e ? col[b + 1] : -1,
-                        b + 2 < e ? col[b + 2] : -1);
+    const int32_t x0 = b < e ? col[b] : -1, x1 = b + 1 < e ? col[b + 1] : -1, x2 = b + 2 < e ? col[b + 2] : -1;
+    head[v] = make_int4((int)(e - b), x0, x1, x2);
+    if (nb4) nb4[v] = make_int4(x0, x1, x2, b + 3 < e ? col[b + 3] : -1);  // (rows of at most four)
   }
 }
 
@@ -1844,6 +1867,7 @@ DevG<RowT> make_devg(bfs_graph *g) {
   G.recs = g->recs;
   G.partials = g->partials;
   G.headc = g->headc;
+  G.nb4 = g->nb4;
   G.hrank = g->hrank;
   G.rpc = g->rpc;
   G.n = g->n;
@@ -2272,10 +2296,10 @@ int build_head(bfs_graph *g) {
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + bs - 1) / bs, 8192));
   if (g->rp64)
     hipLaunchKernelGGL(k_build_head<int64_t>, dim3(blocks), dim3(bs), 0, nullptr,
-                       static_cast<const int64_t *>(g->rp), g->col, g->head, g->n);
+                       static_cast<const int64_t *>(g->rp), g->col, g->head, g->nb4, g->n);
   else
     hipLaunchKernelGGL(k_build_head<int32_t>, dim3(blocks), dim3(bs), 0, nullptr,
-                       static_cast<const int32_t *>(g->rp), g->col, g->head, g->n);
+                       static_cast<const int32_t *>(g->rp), g->col, g->head, g->nb4, g->n);
   if (g->rp64)
     hipLaunchKernelGGL(k_build_headc<int64_t>, dim3(blocks), dim3(bs), 0, nullptr, g->head, g->iso, g->hrank,
                        static_cast<const int64_t *>(g->rp), g->headc, g->rpc, g->words);
