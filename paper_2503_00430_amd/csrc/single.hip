@@ -119,9 +119,9 @@ struct Stage {
   uint64_t *wv;
   unsigned *wp;
   unsigned cap_small, cap_medium, cap_large;
-  __device__ unsigned cap(int b) const {
-    return b == kSmall ? cap_small : (b == kMedium ? cap_medium : cap_large);
-  }
+  // (8, 4 and 2 entries per thread: computed, not looked up, so that a
+  // thread-dependent class does not put the struct in scratch memory)
+  __device__ unsigned cap(int b) const { return (8u * blockDim.x) >> b; }
 };
 
 __host__ __device__ constexpr size_t stage_bytes(int bs) { return 16 + (size_t)76 * bs; }
@@ -1307,18 +1307,18 @@ __global__ void __launch_bounds__(1024) k_td_persistent(DevG<RowT> G, int32_t nb
 //      batch holds a real candidate whatever the density of unvisited
 //      vertices (dense early levels and sparse late ones cost the same per
 //      candidate);
-//   3. each batch of 64 candidates loads its head records (degree and first
-//      three neighbours) and tests them against the frontier bitmap (the
-//      second and third only where the first misses); the next batch's head
-//      records are already in flight while a batch is resolved;
+//   3. each batch of up to 128 candidates (two per lane) loads its head
+//      records (degree and first three neighbours) and tests them against
+//      the frontier bitmap (the second and third only where the first
+//      misses); the next batch's head records are already in flight while a
+//      batch is resolved;
 //   4. candidates that miss and have longer rows go to a deferred ring; once
-//      64 have gathered, the wavefront scans those rows one per lane
-//      (kBuUnroll neighbours per step as independent loads), rows longer
-//      than tbu by the whole wavefront with a ballot early exit;
+//      64 have gathered, the wavefront scans the rest of those rows laid end
+//      to end, a lane per neighbour, two 64-neighbour steps in flight; rows
+//      longer than tbu by the whole wavefront with a ballot early exit;
 //   5. the found masks collect in LDS and are written as next-frontier and
 //      visited words with one coalesced store per run.
 // `examined` counts neighbours up to and including the first hit.
-constexpr int kBuUnroll = 4;
 // A bottom-up wavefront resolves its candidates kBuSub * 64 at a time (lane
 // l holds candidates l, l + 64, ...), so the frontier-word gathers of kBuSub
 // batches are in flight together.
