@@ -161,3 +161,31 @@ def deferred_rows(n=8192, nf=1000, seed=3):
         d = np.full(n, 2, np.int64); d[lo:] = 1; d[0] = 0
         return d
     return g, f
+
+
+def summary_skip(seed=11):
+    """A top-down level whose expected frontier is large but whose actual one
+    is small, followed by a bottom-up level (alpha 75, beta 24).  Source 0 is
+    joined to vertex 1 of a 40-clique in word 0; every clique vertex has two
+    pendants, each alone in one of words 1..80, and every pendant thirty
+    leaves (words 81..118); the upper half is a dense part the source cannot
+    reach, so almost every edge end is unvisited.  Level 2 expands the clique
+    (1 661 edges, about 1 640 expected finds against 4 per bitmap word =
+    1 024) and finds 138; level 3, bottom-up, has a 138-vertex frontier (at
+    most 2 per word = 512): a summary missing the pendants' bits would hide
+    every leaf's frontier neighbour.  Distances: 0, 1 (vertex 1), 2 (the
+    clique and vertex 1's pendants), 3 (the other pendants and vertex 1's
+    pendants' leaves), 4 (the other leaves), unreached elsewhere."""
+    n = 16384
+    rng = np.random.default_rng(seed)
+    core = np.arange(1, 41)
+    pend = 64 * (1 + np.arange(80))
+    leaves = 64 * 81 + np.arange(80 * 30)
+    dense = np.arange(8192, n)
+    m = len(dense) * 9
+    a, b = np.triu_indices(40, 1)
+    u = np.concatenate([[0], core[a], np.repeat(core, 2), np.repeat(pend, 30), rng.choice(dense, m)])
+    v = np.concatenate([[1], core[b], pend, leaves, rng.choice(dense, m)])
+    keep = u != v
+    return graphgen.from_edges(n, u[keep], v[keep], "summary_skip")
+

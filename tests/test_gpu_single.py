@@ -436,3 +436,23 @@ def test_td_visited_needs_td_only(rmat16):
     bfs.bfs_set_params(gh, td_visited=bfs.BFS_TD_VISITED_BITMAP)
     check_single(rmat16, gh, int(graphgen.sources(rmat16, 1)[0]))
     gh.close()
+
+
+@pytest.mark.parametrize("loop", [1, 2, 4])
+def test_summary_skipped_then_small_bottom_up(bfs, loop):
+    """A top-down level that skips the frontier summary (its expected
+    frontier is too large for a bottom-up level to test the summary), then
+    a bottom-up level with a frontier small enough to test it: the summary
+    counts as incomplete, so the level reads the frontier bitmap itself.
+    One bottom-up wavefront, so its runs are long enough to hold summary
+    bytes (tests/test_oracle_policy.py pins the schedule and sizes on the
+    CPU)."""
+    g = graphs.summary_skip()
+    say("summary skip, loop", loop)
+    gh = upload(g)
+    bfs.bfs_set_params(gh, policy=1, alpha=75, beta=24, block_size=64, bu_blocks=1, loop=loop)
+    _, _, run, levels = check_single(g, gh, 0)
+    assert [lv["direction"] for lv in levels] == [0, 0, 0, 1, 1]
+    assert levels[3]["frontier"] == 138 and run["reached"] == 1 + 1 + 41 + 138 + 2340
+    gh.close()
+

@@ -112,3 +112,30 @@ def test_classifier_auto():
     st = oracle.level_stats(r, d)
     assert oracle.replay_policy(st, "auto") == oracle.replay_policy(st, "alpha_beta")
     assert oracle.BU in oracle.replay_policy(st, "auto")
+
+
+def test_summary_skip_graph_premises():
+    """Premises of the GPU test of a skipped frontier summary
+    (tests/graphs.summary_skip): the distances its construction implies, the
+    alpha/beta schedule T T T B B at alpha 75, a level-2 expected frontier
+    m_f * m_u / nnz above 4 vertices per bitmap word (where a top-down level
+    stops keeping the summary) and a level-3 bottom-up frontier of at most 2
+    per word (where a bottom-up level would test it)."""
+    g = graphs.summary_skip()
+    d = oracle.bfs(g, 0, want_parent=False)[0]
+    want = np.full(g.n, -1, np.int64)
+    want[0], want[1] = 0, 1
+    want[2:41] = 2
+    pend = 64 * (1 + np.arange(80))
+    want[pend[:2]] = 2
+    want[pend[2:]] = 3
+    leaves = 64 * 81 + np.arange(80 * 30)
+    want[leaves[:60]] = 3
+    want[leaves[60:]] = 4
+    assert np.array_equal(d, want)
+    st = oracle.level_stats(g, d)
+    words = (g.n + 63) // 64
+    assert st["h"].tolist() == [1, 1, 41, 138, 2340]
+    assert oracle.replay_policy(st, "alpha_beta", 75, 24) == [oracle.TD] * 3 + [oracle.BU] * 2
+    assert st["mf"][2] * st["mu"][2] > 4 * words * st["nnz"]
+    assert st["h"][3] <= 2 * words
