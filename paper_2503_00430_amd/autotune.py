@@ -211,7 +211,8 @@ def main(argv=None):
         table = json.load(open(args.out))
     except (OSError, ValueError):
         table = {}
-    table[graph_class(info)] = tuned
+    # (parameters of modes not run this time stay as they were)
+    table[graph_class(info)] = {**table.get(graph_class(info), {}), **tuned}
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
     print(json.dumps({"class": graph_class(info), "params": tuned}))
