@@ -134,8 +134,12 @@ typedef struct bfs_params {
   int32_t msbfs_block_size;   /* batched search: threads per workgroup (default 256) */
   int32_t msbfs_bu_percent;   /* batched search: a level runs bottom-up when its frontier
                                  edge count exceeds this percent of nnz (default 5) */
-  int32_t graph_td_blocks;    /* GRAPH / PERSISTENT loops: workgroups of the fixed top-down grid
-                                 (default 128) */
+  int32_t graph_td_blocks;    /* GRAPH / PERSISTENT loops: size of the fixed top-down roles
+                                 (default 128).  GRAPH: at most this many workgroups
+                                 for the small-degree role and half as many for the
+                                 medium one, each taking only as many as its queue
+                                 needs; the per-chunk role takes every other workgroup
+                                 of the grid.  PERSISTENT: the cooperative grid. */
   int32_t bu_blocks;          /* bottom-up: workgroups of the grid, each wavefront taking an equal
                                  share of the visited words (0 = automatic: one word per
                                  wavefront up to 1024 workgroups; at most 1024) */
