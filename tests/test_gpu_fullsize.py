@@ -14,7 +14,9 @@ Configurations:
     level loop those parameters select (the captured loop at RMAT scale 24,
     the persistent top-down kernel on the lattice) and with the host-driven
     loop of the instrumented pass;
-  * "default": flags 0 and default parameters.
+  * "default": flags 0 and default parameters;
+  * RMAT scale 24 also in the benchmark's configuration with the paper's
+    alpha = 14, beta = 24, which keeps more hub-heavy levels top-down.
 Workloads: RMAT scale 24 (int64 row offsets, 64 sources), the 4096 x 4096
 perturbed lattice (16 sources) and RMAT scale 16 (int32 row offsets, 16
 sources)."""
@@ -74,7 +76,8 @@ def run_all(bfs, g, gh, rec, parents, pool):
     return len(rec["runs"])
 
 
-CASES = [("rmat24", "bench", None), ("rmat24", "bench", "host"), ("rmat24", "default", None),
+CASES = [("rmat24", "bench", None), ("rmat24", "bench", "host"), ("rmat24", "bench", "alpha14"),
+         ("rmat24", "default", None),
          ("grid4096", "bench", None), ("grid4096", "bench", "host"), ("grid4096", "default", None),
          ("rmat16", "bench", None), ("rmat16", "bench", "host"), ("rmat16", "default", None)]
 
@@ -90,6 +93,10 @@ def test_every_source(bfs, name, config, loop):
     assert info["row_ptr_bytes"] == (4 if rp32 else 8) and info["nnz"] == g.nnz
     if loop == "host":
         bfs.bfs_set_params(gh, loop=bfs.BFS_LOOP_HOST, collect_timing=1)
+    elif loop == "alpha14":
+        # the paper's alpha / beta: more hub-heavy levels stay top-down, and
+        # those skip the frontier summary (checked against the same replay)
+        bfs.bfs_set_params(gh, policy=1, alpha=14, beta=24)
     say(name, config, loop or "graph", "params", bfs.bfs_get_params(gh))
     # parents of every source in the benchmark's own configuration
     with ThreadPoolExecutor(8) as pool:
@@ -100,5 +107,7 @@ def test_every_source(bfs, name, config, loop):
     # benchmark's configuration; AUTO runs the captured loop)
     tuned_loop = bfs.bfs_get_params(gh)["loop"]
     expect_loop = bfs.BFS_LOOP_HOST if loop == "host" else (tuned_loop or bfs.BFS_LOOP_GRAPH)
+    if loop == "alpha14":
+        assert run["policy"] == 1
     assert run["loop"] == expect_loop
     gh.close()
