@@ -322,18 +322,36 @@ __device__ void publish(Ctl *c) {
 // level 0 in queue set 0
 // (the first level is top-down).
 
+// a[0, n) = -1 except a[s] = sv, with streaming stores: 4-byte stores up to
+// the first 16-byte boundary and past the last, 16-byte stores between.
+__device__ __forceinline__ void init_fill(int32_t *a, int64_t n, int32_t s, int32_t sv, int64_t tid,
+                                          int64_t stride) {
+  typedef int32_t v4i __attribute__((ext_vector_type(4)));
+  const int64_t head = min(n, (int64_t)(((16u - (reinterpret_cast<uintptr_t>(a) & 15u)) & 15u) >> 2));
+  const int64_t groups = (n - head) >> 2;
+  for (int64_t i = tid; i < head; i += stride) __builtin_nontemporal_store(i == s ? sv : -1, gptr(a + i));
+  v4i *a4 = reinterpret_cast<v4i *>(a + head);
+  for (int64_t q = tid; q < groups; q += stride) {
+    const int64_t i0 = head + 4 * q;
+    v4i x = {-1, -1, -1, -1};
+    if (s >= i0 && s < i0 + 4) x[s - i0] = sv;
+    __builtin_nontemporal_store(x, a4 + q);
+  }
+  for (int64_t i = head + 4 * groups + tid; i < n; i += stride)
+    __builtin_nontemporal_store(i == s ? sv : -1, gptr(a + i));
+}
+
 template <class RowT>
 __global__ void k_init(DevG<RowT> G, int32_t s, int32_t *dist, int32_t *parent, int32_t policy,
                        int32_t alpha, int32_t beta, int64_t nnz, int32_t rec_cap, Ctl *mirror,
                        uint32_t seq0, int32_t pub_mode) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = tid; i < G.n; i += stride) {
-    // streaming stores: left dirty in the caches, these lines would be
-    // written back during the first dense level and slow it (-5 % per search)
-    __builtin_nontemporal_store((i == s) ? 0 : -1, gptr(dist + i));
-    if (parent) __builtin_nontemporal_store((i == s) ? s : -1, gptr(parent + i));
-  }
+  // streaming stores: left dirty in the caches, these lines would be written
+  // back during the first dense level and slow it (-5 % per search); 16
+  // bytes a lane over the 16-byte-aligned middle of each array
+  init_fill(dist, G.n, s, 0, tid, stride);
+  if (parent) init_fill(parent, G.n, s, s, tid, stride);
   const int64_t sw = s >> 6;
   const uint64_t sb = 1ull << (s & 63);
   for (int64_t w = tid; w < G.words; w += stride) {
