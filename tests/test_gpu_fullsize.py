@@ -16,7 +16,9 @@ Configurations:
     loop of the instrumented pass;
   * "default": flags 0 and default parameters;
   * RMAT scale 24 also in the benchmark's configuration with the paper's
-    alpha = 14, beta = 24, which keeps more hub-heavy levels top-down.
+    alpha = 14, beta = 24 (more hub-heavy levels stay top-down), with the
+    5 % frontier rule, and top-down only in the captured loop and in the
+    persistent kernel (every hub level expanded top-down).
 Workloads: RMAT scale 24 (int64 row offsets, 64 sources), the 4096 x 4096
 perturbed lattice (16 sources) and RMAT scale 16 (int32 row offsets, 16
 sources)."""
@@ -77,6 +79,7 @@ def run_all(bfs, g, gh, rec, parents, pool):
 
 
 CASES = [("rmat24", "bench", None), ("rmat24", "bench", "host"), ("rmat24", "bench", "alpha14"),
+         ("rmat24", "bench", "pct5"), ("rmat24", "bench", "tdonly"), ("rmat24", "bench", "tdonly_persistent"),
          ("rmat24", "default", None),
          ("grid4096", "bench", None), ("grid4096", "bench", "host"), ("grid4096", "default", None),
          ("rmat16", "bench", None), ("rmat16", "bench", "host"), ("rmat16", "default", None)]
@@ -97,6 +100,12 @@ def test_every_source(bfs, name, config, loop):
         # the paper's alpha / beta: more hub-heavy levels stay top-down, and
         # those skip the frontier summary (checked against the same replay)
         bfs.bfs_set_params(gh, policy=1, alpha=14, beta=24)
+    elif loop == "pct5":
+        bfs.bfs_set_params(gh, policy=2)  # the 5 % frontier rule
+    elif loop == "tdonly":
+        bfs.bfs_set_params(gh, policy=3)  # every hub level through the per-chunk role
+    elif loop == "tdonly_persistent":
+        bfs.bfs_set_params(gh, policy=3, loop=bfs.BFS_LOOP_PERSISTENT)
     say(name, config, loop or "graph", "params", bfs.bfs_get_params(gh))
     # parents of every source in the benchmark's own configuration
     with ThreadPoolExecutor(8) as pool:
@@ -109,5 +118,9 @@ def test_every_source(bfs, name, config, loop):
     expect_loop = bfs.BFS_LOOP_HOST if loop == "host" else (tuned_loop or bfs.BFS_LOOP_GRAPH)
     if loop == "alpha14":
         assert run["policy"] == 1
+    elif loop in ("pct5", "tdonly", "tdonly_persistent"):
+        assert run["policy"] == (2 if loop == "pct5" else 3)
+    if loop == "tdonly_persistent":
+        expect_loop = bfs.BFS_LOOP_PERSISTENT
     assert run["loop"] == expect_loop
     gh.close()
